@@ -1,0 +1,185 @@
+/*
+ * ising.h -- C ABI of the MI355X (gfx950) library for replica-parallel
+ * checkerboard Metropolis annealing on +/-1-weighted toroidal Ising /
+ * Max-Cut instances.
+ *
+ * Problem (paper, Section II): maximise the cut of eq. (1),
+ *     cut(x) = 1/2 sum_{i<j} w_ij (1 - x_i x_j),  x in {-1,+1}^n,
+ * which is the same as minimising the Ising energy of eq. (2) with
+ * J_ij = -w_ij and h_i = 0:  H(s) = sum_{i<j} w_ij s_i s_j = W_total - 2 cut(s),
+ * every edge counted once.  Instances (Section I; Appendix A, Fig. 2) are
+ * toroidal grids with nearest-neighbour couplings w_ij in {-1,+1}; the 3-D
+ * cubic torus (six neighbours) is the same family with one more axis.
+ * A trial (Section III) is a run of S sweeps whose state is read out at its
+ * end; trial length in sweeps is its only parameter.  The paper withholds its
+ * own update rule, so a sweep here is one checkerboard Metropolis pass:
+ * every site of colour 0, then every site of colour 1, each proposing one
+ * flip, accepted when the energy change dE <= 0 or when a Philox4x32-10 word
+ * u < floor(2^32 exp(-beta_t dE)).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns ISING_OK (0) or a negative ISING_E_* code; no C++
+ *    exception crosses this boundary.  ising_last_error() gives a message for
+ *    the last failing call on the calling thread.
+ *  - Argument errors are reported synchronously.  GPU work is enqueued on the
+ *    caller's HIP stream (`stream` is a hipStream_t; NULL = the null stream)
+ *    and returns before it completes; a fault in it surfaces as ISING_E_HIP
+ *    from a later call or from the caller's own synchronisation.
+ *  - Spin buffers use the canonical layout: int8 [R][n], row-major per
+ *    replica, value +1 or -1, site i = row-major index of its coordinates
+ *    (2-D {rows, cols}: i = r*cols + c; 3-D {Lz, Ly, Lx}: i = (z*Ly + y)*Lx + x).
+ *    Edge e = ndim*i + d joins site i to its +1 neighbour along the d-th
+ *    fastest axis (2-D: d = 0 column, d = 1 row; 3-D: d = 0 x, 1 y, 2 z).
+ *  - The caller owns every buffer it passes; the library never frees them.
+ *    Device pointers must be device memory of the current HIP device.
+ *  - Random numbers: Philox4x32-10 with key = seed (low word, high word) and
+ *    counter (c0, c1, c2, c3); tags in c3: 0 Metropolis draw (c0 = site,
+ *    c1 = sweep, c2 = replica >> 2, word replica & 3), 1 initial spin (c0 =
+ *    site, c1 = 0, c2 = replica >> 2, word replica & 3, +1 iff top bit set),
+ *    2 edge weight (c0 = edge >> 2, c1 = c2 = 0, word edge & 3, +1 iff top
+ *    bit set).  Trajectories are therefore reproducible bit for bit and do
+ *    not depend on launch shape or packing.
+ */
+#ifndef ISING_H
+#define ISING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ISING_OK = 0,
+  ISING_E_ARG = -1,          /* invalid argument (value, pointer or range)          */
+  ISING_E_TOPOLOGY = -2,     /* torus shape not supported (odd or < 2 dimension)    */
+  ISING_E_NOMEM = -3,        /* host or device allocation failed                    */
+  ISING_E_HIP = -4,          /* HIP runtime error (includes errors of earlier work) */
+  ISING_E_UNSUPPORTED = -5,  /* valid request this build cannot run (e.g. too large)*/
+  ISING_E_STATE = -6         /* object in the wrong state for the call              */
+};
+
+enum { ISING_SCHED_LINEAR = 0, ISING_SCHED_GEOMETRIC = 1, ISING_SCHED_TABLE = 2 };
+
+/* Internal packing of the replicas; results do not depend on it. */
+enum {
+  ISING_LAYOUT_AUTO = 0,  /* library chooses (autotuned where a tuning exists)  */
+  ISING_LAYOUT_I8 = 1,    /* 4 replicas per 32-bit word: spin + maintained field */
+  ISING_LAYOUT_BP32 = 2   /* 32 replicas per 32-bit word: one spin bit each      */
+};
+
+/* A cut or energy that could not be computed because the replica's spins
+ * held a value other than +1 / -1. */
+#define ISING_INVALID_VALUE INT64_MIN
+
+typedef struct ising_graph ising_graph;
+
+/*
+ * Build a torus instance (paper, Section I and Appendix A: toroidal grid,
+ * nearest-neighbour +/-1 couplings, periodic boundaries).
+ *   ndim         2 or 3.
+ *   dims         host int32[ndim]: 2-D {rows, cols}, 3-D {Lz, Ly, Lx}; every
+ *                entry even and >= 2 (the checkerboard needs a bipartite
+ *                torus), else ISING_E_TOPOLOGY.  A length of 2 gives two
+ *                parallel edges between the same pair, each with its weight.
+ *                n = product of dims must be < 2^31 / ndim.
+ *   weight_seed  used when weights == NULL: w_e = +1 iff the top bit of word
+ *                (e & 3) of Philox(weight_seed, (e >> 2, 0, 0, 2)) is set.
+ *   weights      NULL, or host int8[ndim * n] of +1 / -1 in edge order
+ *                (anything else: ISING_E_ARG).
+ *   out          receives the handle (owns its host and device copies of the
+ *                instance; created on the current HIP device).
+ * Synchronous.
+ */
+int ising_create_graph(int32_t ndim, const int32_t* dims, uint64_t weight_seed,
+                       const int8_t* weights, ising_graph** out);
+
+/* Free a graph (NULL-safe).  Work that uses it must have completed. */
+void ising_destroy_graph(ising_graph* g);
+
+/* Sizes of an instance; any output pointer may be NULL.  w_total = sum of
+ * all edge weights, so that energy = w_total - 2 cut (eq. (1), eq. (2)). */
+int ising_graph_info(const ising_graph* g, int64_t* n_spins, int64_t* n_edges,
+                     int64_t* w_total, int32_t* degree);
+
+/* Copy the edge weights (edge order) to host int8[n_edges]. */
+int ising_graph_weights(const ising_graph* g, int8_t* host_out);
+
+/* Host-only: the weights ising_create_graph(ndim, dims, weight_seed, NULL)
+ * would generate, into host int8[ndim * n].  Needs no GPU. */
+int ising_generate_weights(int32_t ndim, const int32_t* dims, uint64_t weight_seed,
+                           int8_t* host_out);
+
+/* Parameters of a run of trials. */
+typedef struct {
+  uint32_t struct_size;      /* = sizeof(ising_run_params)                           */
+  int32_t layout;            /* ISING_LAYOUT_*                                       */
+  uint64_t seed;             /* Philox key of the run                                */
+  int32_t n_replicas;        /* R >= 1: independent trials                           */
+  int32_t n_sweeps;          /* S >= 1: trial length of the schedule (Section III)   */
+  int32_t sweep_begin;       /* window [sweep_begin, sweep_end) of that schedule     */
+  int32_t sweep_end;         /* 0 <= begin < end <= S                                */
+  int32_t schedule;          /* ISING_SCHED_*                                        */
+  int32_t init_spins;        /* 1: Philox initial state (needs begin == 0);          */
+                             /* 0: start from spins_inout                            */
+  double beta0, beta1;       /* linear: beta0 + (beta1-beta0)*(t/(S-1)), both >= 0;  */
+                             /* geometric: beta0*(beta1/beta0)^(t/(S-1)), both > 0;  */
+                             /* S == 1 gives beta0                                   */
+  const double* beta_table;  /* host double[S], every entry >= 0, when TABLE         */
+  int32_t block_threads;     /* 0: library default / tuned; else threads per block   */
+                             /* (rounded to the kernel's granularity)                */
+  int32_t replica_offset;    /* global id of replica 0 of this call (Philox streams */
+                             /* are keyed by global ids); multiple of 4 (i8) or 32   */
+                             /* (bp32); normally 0                                   */
+  uint64_t* stats_out;       /* device uint64[2] or NULL: the run adds the number of */
+                             /* Philox4x32-10 blocks it evaluated to [0] and the     */
+                             /* number of attempts that needed a uniform (dE > 0 and */
+                             /* a nonzero threshold) to [1]                          */
+} ising_run_params;
+
+/*
+ * Run sweeps [sweep_begin, sweep_end) of the S-sweep schedule on R replicas.
+ * Sweep t runs at beta_t; an energy change dE = 4k > 0 is accepted iff
+ * u < T_k(t) = min(2^32 - 1, floor(2^32 exp(-4 k beta_t))) (the table
+ * ising_thresholds returns), u = Philox word of (site, t, replica).
+ *   spins_inout  device int8 [R][n], canonical layout: the window's initial
+ *                state (ignored when init_spins) and, on completion, its
+ *                final state.
+ *   cut_out      device int64 [R] or NULL: eq. (1) cut of the final state.
+ *   energy_out   device int64 [R] or NULL: eq. (2) energy of the final state.
+ *                A replica whose input held a value other than +1/-1 gets
+ *                ISING_INVALID_VALUE in both (its run takes values > 0 as
+ *                +1 and all others as -1).
+ *   flips_out    device uint32 [R] or NULL: accepted flips in the window
+ *                (modulo 2^32).
+ * Asynchronous on `stream`.
+ */
+int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout,
+                     int64_t* cut_out, int64_t* energy_out, uint32_t* flips_out, void* stream);
+
+/*
+ * Exact cut (eq. (1)) and energy (eq. (2), J = -w, h = 0) of R states.
+ *   spins        device int8 [n_replicas][n], canonical layout.
+ *   cut_out, energy_out  device int64 [n_replicas]; either may be NULL.
+ *   A replica holding a value other than +1 / -1 gets ISING_INVALID_VALUE.
+ * Asynchronous on `stream`.
+ */
+int ising_eval_cut(const ising_graph* g, const int8_t* spins, int64_t n_replicas,
+                   int64_t* cut_out, int64_t* energy_out, void* stream);
+
+/* Host-only: the acceptance thresholds T_k(t), k = 1..degree/2, of the whole
+ * S-sweep schedule of p, into host uint32 [S][degree/2].  degree is 4 or 6. */
+int ising_thresholds(const ising_run_params* p, int32_t degree, uint32_t* host_out);
+
+/* Philox4x32-10 blocks on the GPU (the generator the kernels use), for
+ * cross-checks: device uint32 ctr[m][4] in, device uint32 out[m][4] out.
+ * Asynchronous on `stream`. */
+int ising_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ising_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISING_H */

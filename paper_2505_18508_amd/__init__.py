@@ -1,0 +1,228 @@
+"""Python binding of libising.so, the MI355X (gfx950) library for
+replica-parallel checkerboard Metropolis annealing on +/-1 toroidal Ising /
+Max-Cut instances (paper: maximise eq. (1); Ising form eq. (2) with J = -w,
+h = 0; trial length in sweeps, Section III).
+
+This module only marshals arguments to the C ABI declared in
+include/ising.h; every step of the computation runs in the library's HIP
+kernels.  torch is used for device memory and streams only.  If the library
+has not been built the import of the binding fails loudly: there is no CPU
+fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libising.so")
+
+OK, E_ARG, E_TOPOLOGY, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_TABLE = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_I8, LAYOUT_BP32 = 0, 1, 2
+INVALID_VALUE = -(2**63)
+
+SCHEDULES = {"linear": SCHED_LINEAR, "geometric": SCHED_GEOMETRIC, "table": SCHED_TABLE}
+LAYOUTS = {"auto": LAYOUT_AUTO, "i8": LAYOUT_I8, "bp32": LAYOUT_BP32}
+
+EXPORTED = [
+    "ising_create_graph", "ising_destroy_graph", "ising_graph_info", "ising_graph_weights",
+    "ising_generate_weights", "ising_run_trials", "ising_eval_cut", "ising_thresholds",
+    "ising_philox_dump", "ising_last_error",
+]
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("ising error %d: %s" % (code, message))
+        self.code = code
+
+
+class RunParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("layout", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("n_replicas", ctypes.c_int32),
+        ("n_sweeps", ctypes.c_int32),
+        ("sweep_begin", ctypes.c_int32),
+        ("sweep_end", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
+        ("init_spins", ctypes.c_int32),
+        ("beta0", ctypes.c_double),
+        ("beta1", ctypes.c_double),
+        ("beta_table", ctypes.c_void_p),
+        ("block_threads", ctypes.c_int32),
+        ("replica_offset", ctypes.c_int32),
+        ("stats_out", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libising.so is not built (run paper_2505_18508_amd/build.py): %s" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        L.ising_create_graph.argtypes = [i32, vp, u64, vp, ctypes.POINTER(vp)]
+        L.ising_destroy_graph.argtypes = [vp]
+        L.ising_destroy_graph.restype = None
+        L.ising_graph_info.argtypes = [vp, vp, vp, vp, vp]
+        L.ising_graph_weights.argtypes = [vp, vp]
+        L.ising_generate_weights.argtypes = [i32, vp, u64, vp]
+        L.ising_run_trials.argtypes = [vp, ctypes.POINTER(RunParams), vp, vp, vp, vp, vp]
+        L.ising_eval_cut.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.ising_thresholds.argtypes = [ctypes.POINTER(RunParams), i32, vp]
+        L.ising_philox_dump.argtypes = [u64, vp, i64, vp, vp]
+        L.ising_last_error.argtypes = []
+        L.ising_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name != "ising_destroy_graph" and name != "ising_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise IsingError(rc, lib().ising_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _dims_arr(dims):
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    return d, d.ctypes.data
+
+
+class Graph:
+    """A torus instance (handle of ising_create_graph) on the current device."""
+
+    def __init__(self, dims, weight_seed=0, weights=None):
+        d, dp = _dims_arr(dims)
+        self.dims = [int(x) for x in d]
+        h = ctypes.c_void_p()
+        wp = None
+        if weights is not None:
+            w = np.ascontiguousarray(weights, dtype=np.int8)
+            wp = w.ctypes.data
+        _check(lib().ising_create_graph(len(d), dp, int(weight_seed), wp, ctypes.byref(h)))
+        self._h = h
+        n, ne, wt, deg = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().ising_graph_info(h, ctypes.byref(n), ctypes.byref(ne), ctypes.byref(wt), ctypes.byref(deg)))
+        self.n, self.n_edges, self.w_total, self.degree = n.value, ne.value, wt.value, deg.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def weights(self):
+        out = np.zeros(self.n_edges, np.int8)
+        _check(lib().ising_graph_weights(self._h, out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ising_destroy_graph(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_graph(dims, weight_seed=0, weights=None):
+    return Graph(dims, weight_seed, weights)
+
+
+def generate_weights(dims, weight_seed):
+    d, dp = _dims_arr(dims)
+    out = np.zeros(len(d) * int(np.prod(d)), np.int8)
+    _check(lib().ising_generate_weights(len(d), dp, int(weight_seed), out.ctypes.data))
+    return out
+
+
+def make_params(seed, n_replicas, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,
+                beta1=3.0, beta_table=None, init_spins=True, layout="auto", block_threads=0, replica_offset=0,
+                stats=None):
+    """RunParams plus the objects whose memory it points to (keep both alive)."""
+    p = RunParams()
+    p.struct_size = ctypes.sizeof(RunParams)
+    p.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    p.seed = int(seed)
+    p.n_replicas = int(n_replicas)
+    p.n_sweeps = int(n_sweeps)
+    p.sweep_begin = int(sweep_begin)
+    p.sweep_end = int(n_sweeps if sweep_end is None else sweep_end)
+    p.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+    p.init_spins = 1 if init_spins else 0
+    p.beta0 = float(beta0)
+    p.beta1 = float(beta1)
+    keep = None
+    if beta_table is not None:
+        keep = np.ascontiguousarray(beta_table, dtype=np.float64)
+        p.beta_table = keep.ctypes.data
+    p.block_threads = int(block_threads)
+    p.replica_offset = int(replica_offset)
+    p.stats_out = None if stats is None else _ptr(stats).value
+    return p, keep
+
+
+def run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,
+               beta1=3.0, beta_table=None, init_spins=True, layout="auto", cut=None, energy=None, flips=None,
+               block_threads=0, replica_offset=0, stats=None, stream=None):
+    """ising_run_trials on device tensors: spins int8 [R][n] (in/out); cut,
+    energy int64 [R], flips uint32/int32 [R], stats int64 [2] optional.
+    Asynchronous."""
+    R = spins.shape[0]
+    if spins.dim() != 2 or spins.shape[1] != graph.n:
+        raise ValueError("spins must be [R][%d]" % graph.n)
+    p, keep = make_params(seed, R, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1, beta_table,
+                          init_spins, layout, block_threads, replica_offset, stats)
+    _check(lib().ising_run_trials(graph.handle, ctypes.byref(p), _ptr(spins), _ptr(cut), _ptr(energy), _ptr(flips),
+                                  _stream(stream)))
+    del keep
+
+
+def eval_cut(graph, spins, cut=None, energy=None, stream=None):
+    if spins.dim() != 2 or spins.shape[1] != graph.n:
+        raise ValueError("spins must be [R][%d]" % graph.n)
+    _check(lib().ising_eval_cut(graph.handle, _ptr(spins), spins.shape[0], _ptr(cut), _ptr(energy), _stream(stream)))
+
+
+def thresholds(n_sweeps, schedule="linear", beta0=0.1, beta1=3.0, beta_table=None, degree=4):
+    """Acceptance thresholds T_k(t) of a whole schedule: uint32 [S][degree/2]."""
+    p, keep = make_params(0, 1, n_sweeps, 0, None, schedule, beta0, beta1, beta_table)
+    out = np.zeros((n_sweeps, degree // 2), np.uint32)
+    _check(lib().ising_thresholds(ctypes.byref(p), int(degree), out.ctypes.data))
+    del keep
+    return out
+
+
+def philox_dump(key, ctr, out, stream=None):
+    """Philox4x32-10 blocks on the GPU: ctr, out uint32/int32 device [m][4]."""
+    _check(lib().ising_philox_dump(int(key), _ptr(ctr), ctr.shape[0], _ptr(out), _stream(stream)))

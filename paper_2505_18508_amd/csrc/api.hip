@@ -1,0 +1,407 @@
+// C ABI of the library (declared in include/ising.h): argument checking,
+// instance construction, schedules and acceptance thresholds, kernel
+// selection.  All GPU work is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ising.h"
+#include "internal.hpp"
+#include "philox.hpp"
+
+using ising::Lattice;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct DeviceInfo {
+  int cus = 0;
+  size_t lds_per_block = 0;
+};
+
+DeviceInfo device_info(int dev) {
+  static std::mutex mu;
+  static std::vector<DeviceInfo> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1);
+  if (cache[dev].cus == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      cache[dev].cus = prop.multiProcessorCount;
+      cache[dev].lds_per_block = prop.sharedMemPerBlock;
+    }
+  }
+  return cache[dev];
+}
+
+int check_dims(int32_t ndim, const int32_t* dims) {
+  if (ndim != 2 && ndim != 3) return fail(ISING_E_TOPOLOGY, "ndim must be 2 or 3 (got %d)", ndim);
+  if (!dims) return fail(ISING_E_ARG, "dims is NULL");
+  int64_t n = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (dims[d] < 2 || (dims[d] & 1))
+      return fail(ISING_E_TOPOLOGY, "dimension %d has length %d; every length must be even and >= 2", d, dims[d]);
+    n *= dims[d];
+    if (n * ndim >= ((int64_t)1 << 31)) return fail(ISING_E_UNSUPPORTED, "torus too large (n * ndim >= 2^31)");
+  }
+  return ISING_OK;
+}
+
+void generate_weights(int32_t ndim, int64_t n, uint64_t seed, int8_t* out) {
+  const int64_t ne = ndim * n;
+  for (int64_t blk = 0; blk * 4 < ne; ++blk) {
+    const ising::u32x4 u = ising::philox_ref(seed, (uint32_t)blk, 0u, 0u, ising::kTagWeight);
+    for (int k = 0; k < 4 && blk * 4 + k < ne; ++k) out[blk * 4 + k] = (u.v[k] >> 31) ? 1 : -1;
+  }
+}
+
+// Per-site weight sign bits (direction order +x, -x, +y, -y, +z, -z; bit set:
+// weight -1), in colour-split order.
+std::vector<uint8_t> site_weight_bits(const Lattice& L, const std::vector<int8_t>& w) {
+  std::vector<uint8_t> bits(L.n, 0);
+  const int nd = L.ndim;
+  for (int64_t z = 0; z < L.Lz; ++z)
+    for (int64_t y = 0; y < L.Ly; ++y)
+      for (int64_t x = 0; x < L.Lx; ++x) {
+        auto idx = [&](int64_t xx, int64_t yy, int64_t zz) { return (zz * L.Ly + yy) * L.Lx + xx; };
+        const int64_t i = idx(x, y, z);
+        int8_t ws[6];
+        ws[0] = w[nd * i + 0];
+        ws[1] = w[nd * idx((x + L.Lx - 1) % L.Lx, y, z) + 0];
+        ws[2] = w[nd * i + 1];
+        ws[3] = w[nd * idx(x, (y + L.Ly - 1) % L.Ly, z) + 1];
+        if (nd == 3) {
+          ws[4] = w[nd * i + 2];
+          ws[5] = w[nd * idx(x, y, (z + L.Lz - 1) % L.Lz) + 2];
+        }
+        uint8_t b = 0;
+        for (int d = 0; d < 2 * nd; ++d) b |= (ws[d] < 0 ? 1 : 0) << d;
+        int p;
+        uint32_t h;
+        ising::site_to_split(L, (uint32_t)i, p, h);
+        bits[(size_t)p * L.half + h] = b;
+      }
+  return bits;
+}
+
+int check_params(const ising_run_params* p) {
+  if (!p) return fail(ISING_E_ARG, "params is NULL");
+  if (p->struct_size != sizeof(ising_run_params))
+    return fail(ISING_E_ARG, "params.struct_size is %u, this library expects %zu", p->struct_size,
+                sizeof(ising_run_params));
+  if (p->n_sweeps < 1) return fail(ISING_E_ARG, "n_sweeps must be >= 1");
+  switch (p->schedule) {
+    case ISING_SCHED_LINEAR:
+      if (!(p->beta0 >= 0.0) || !(p->beta1 >= 0.0) || !std::isfinite(p->beta0) || !std::isfinite(p->beta1))
+        return fail(ISING_E_ARG, "linear schedule needs finite beta0, beta1 >= 0");
+      break;
+    case ISING_SCHED_GEOMETRIC:
+      if (!(p->beta0 > 0.0) || !(p->beta1 > 0.0) || !std::isfinite(p->beta0) || !std::isfinite(p->beta1))
+        return fail(ISING_E_ARG, "geometric schedule needs finite beta0, beta1 > 0");
+      break;
+    case ISING_SCHED_TABLE:
+      if (!p->beta_table) return fail(ISING_E_ARG, "table schedule needs beta_table");
+      for (int32_t t = 0; t < p->n_sweeps; ++t)
+        if (!(p->beta_table[t] >= 0.0) || !std::isfinite(p->beta_table[t]))
+          return fail(ISING_E_ARG, "beta_table[%d] is not a finite value >= 0", t);
+      break;
+    default:
+      return fail(ISING_E_ARG, "unknown schedule %d", p->schedule);
+  }
+  return ISING_OK;
+}
+
+// Inverse temperature of sweep t and the acceptance thresholds of an energy
+// increase of 4k, k = 1..kmax.  The schedule is a reading (the paper fixes the
+// trial length in sweeps only); thresholds implement min(1, exp(-beta dE)) for
+// a uniform 32-bit word: accept iff u < floor(2^32 exp(-4 k beta)).
+double schedule_beta(const ising_run_params* p, int32_t t) {
+  if (p->schedule == ISING_SCHED_TABLE) return p->beta_table[t];
+  if (p->n_sweeps == 1) return p->beta0;
+  const double frac = (double)t / (double)(p->n_sweeps - 1);
+  if (p->schedule == ISING_SCHED_LINEAR) return p->beta0 + (p->beta1 - p->beta0) * frac;
+  return p->beta0 * std::pow(p->beta1 / p->beta0, frac);
+}
+
+uint32_t accept_threshold(double beta, int k) {
+  const double scaled = std::ldexp(std::exp(-(double)(4 * k) * beta), 32);
+  return scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
+}
+
+void fill_thresholds(const ising_run_params* p, int kmax, uint32_t* out) {
+  for (int32_t t = 0; t < p->n_sweeps; ++t) {
+    const double beta = schedule_beta(p, t);
+    for (int k = 1; k <= kmax; ++k) out[(size_t)t * kmax + (k - 1)] = accept_threshold(beta, k);
+  }
+}
+
+uint64_t fnv1a(const void* data, size_t bytes) {
+  const unsigned char* c = (const unsigned char*)data;
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+constexpr size_t kMaxCachedTables = 64;
+
+// Device threshold table of p's whole schedule, cached on the graph.  Cached
+// tables are immutable and freed with the graph; beyond the cache size a
+// stream-ordered allocation is made and released after the launch.
+int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t stream, uint32_t** out,
+                    bool* owned) {
+  const int kmax = g->degree / 2;
+  const uint64_t th = p->schedule == ISING_SCHED_TABLE ? fnv1a(p->beta_table, sizeof(double) * p->n_sweeps) : 0;
+  const double b0 = p->schedule == ISING_SCHED_TABLE ? 0.0 : p->beta0;
+  const double b1 = p->schedule == ISING_SCHED_TABLE ? 0.0 : p->beta1;
+  {
+    std::lock_guard<std::mutex> lock(g->mu);
+    for (const ThrCacheEntry& e : g->thr_cache)
+      if (e.schedule == p->schedule && e.n_sweeps == p->n_sweeps && e.kmax == kmax && e.beta0 == b0 &&
+          e.beta1 == b1 && e.table_hash == th) {
+        *out = e.d_thr;
+        *owned = false;
+        return ISING_OK;
+      }
+  }
+  std::vector<uint32_t> host((size_t)p->n_sweeps * kmax);
+  fill_thresholds(p, kmax, host.data());
+  const size_t bytes = host.size() * sizeof(uint32_t);
+  std::lock_guard<std::mutex> lock(g->mu);
+  if (g->thr_cache.size() < kMaxCachedTables) {
+    uint32_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(ISING_E_NOMEM, "threshold table (%zu bytes): %s", bytes, hipGetErrorString(e));
+    e = hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail_hip(e, "threshold table upload");
+    }
+    g->thr_cache.push_back(ThrCacheEntry{p->schedule, p->n_sweeps, kmax, b0, b1, th, d});
+    *out = d;
+    *owned = false;
+    return ISING_OK;
+  }
+  uint32_t* d = nullptr;
+  hipError_t e = hipMallocAsync((void**)&d, bytes, stream);
+  if (e != hipSuccess) return fail(ISING_E_NOMEM, "threshold table (%zu bytes): %s", bytes, hipGetErrorString(e));
+  e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host buffer is released on return
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(d, stream);
+    return fail_hip(e, "threshold table upload");
+  }
+  *out = d;
+  *owned = true;
+  return ISING_OK;
+}
+
+int check_device(const ising_graph* g) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (dev != g->device)
+    return fail(ISING_E_STATE, "graph lives on device %d but device %d is current", g->device, dev);
+  return ISING_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ising_last_error(void) { return g_last_error.c_str(); }
+
+int ising_generate_weights(int32_t ndim, const int32_t* dims, uint64_t weight_seed, int8_t* host_out) {
+  int rc = check_dims(ndim, dims);
+  if (rc) return rc;
+  if (!host_out) return fail(ISING_E_ARG, "host_out is NULL");
+  const Lattice L = ising::make_lattice(ndim, dims);
+  generate_weights(ndim, L.n, weight_seed, host_out);
+  return ISING_OK;
+}
+
+int ising_create_graph(int32_t ndim, const int32_t* dims, uint64_t weight_seed, const int8_t* weights,
+                       ising_graph** out) {
+  if (!out) return fail(ISING_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_dims(ndim, dims);
+  if (rc) return rc;
+  ising_graph* g = new (std::nothrow) ising_graph();
+  if (!g) return fail(ISING_E_NOMEM, "graph handle");
+  g->ndim = ndim;
+  for (int d = 0; d < 3; ++d) g->dims[d] = d < ndim ? dims[d] : 0;
+  g->lat = ising::make_lattice(ndim, dims);
+  g->n = g->lat.n;
+  g->n_edges = (int64_t)ndim * g->n;
+  g->degree = 2 * ndim;
+  try {
+    g->w_host.resize((size_t)g->n_edges);
+  } catch (...) {
+    delete g;
+    return fail(ISING_E_NOMEM, "host weights");
+  }
+  if (weights) {
+    for (int64_t e = 0; e < g->n_edges; ++e) {
+      if (weights[e] != 1 && weights[e] != -1) {
+        delete g;
+        return fail(ISING_E_ARG, "weights[%lld] = %d; weights must be +1 or -1", (long long)e, (int)weights[e]);
+      }
+    }
+    std::memcpy(g->w_host.data(), weights, (size_t)g->n_edges);
+  } else {
+    generate_weights(ndim, g->n, weight_seed, g->w_host.data());
+  }
+  g->w_total = 0;
+  for (int8_t v : g->w_host) g->w_total += v;
+  std::vector<uint8_t> bits = site_weight_bits(g->lat, g->w_host);
+
+  hipError_t e = hipGetDevice(&g->device);
+  if (e != hipSuccess) {
+    delete g;
+    return fail_hip(e, "hipGetDevice");
+  }
+  e = hipMalloc(&g->d_w, (size_t)g->n_edges);
+  if (e == hipSuccess) e = hipMalloc(&g->d_wbits, (size_t)g->n);
+  if (e != hipSuccess) {
+    (void)hipFree(g->d_w);
+    (void)hipFree(g->d_wbits);
+    delete g;
+    return fail(e == hipErrorOutOfMemory ? ISING_E_NOMEM : ISING_E_HIP, "graph device tables: %s",
+                hipGetErrorString(e));
+  }
+  e = hipMemcpy(g->d_w, g->w_host.data(), (size_t)g->n_edges, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(g->d_wbits, bits.data(), (size_t)g->n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(g->d_w);
+    (void)hipFree(g->d_wbits);
+    delete g;
+    return fail_hip(e, "graph upload");
+  }
+  *out = g;
+  return ISING_OK;
+}
+
+void ising_destroy_graph(ising_graph* g) {
+  if (!g) return;
+  (void)hipFree(g->d_w);
+  (void)hipFree(g->d_wbits);
+  for (ThrCacheEntry& e : g->thr_cache) (void)hipFree(e.d_thr);
+  delete g;
+}
+
+int ising_graph_info(const ising_graph* g, int64_t* n_spins, int64_t* n_edges, int64_t* w_total, int32_t* degree) {
+  if (!g) return fail(ISING_E_ARG, "graph is NULL");
+  if (n_spins) *n_spins = g->n;
+  if (n_edges) *n_edges = g->n_edges;
+  if (w_total) *w_total = g->w_total;
+  if (degree) *degree = g->degree;
+  return ISING_OK;
+}
+
+int ising_graph_weights(const ising_graph* g, int8_t* host_out) {
+  if (!g) return fail(ISING_E_ARG, "graph is NULL");
+  if (!host_out) return fail(ISING_E_ARG, "host_out is NULL");
+  std::memcpy(host_out, g->w_host.data(), (size_t)g->n_edges);
+  return ISING_OK;
+}
+
+int ising_thresholds(const ising_run_params* p, int32_t degree, uint32_t* host_out) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (degree != 4 && degree != 6) return fail(ISING_E_ARG, "degree must be 4 or 6");
+  if (!host_out) return fail(ISING_E_ARG, "host_out is NULL");
+  fill_thresholds(p, degree / 2, host_out);
+  return ISING_OK;
+}
+
+int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout, int64_t* cut_out,
+                     int64_t* energy_out, uint32_t* flips_out, void* stream) {
+  if (!g) return fail(ISING_E_ARG, "graph is NULL");
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (p->n_replicas < 1) return fail(ISING_E_ARG, "n_replicas must be >= 1");
+  if (p->sweep_begin < 0 || p->sweep_end > p->n_sweeps || p->sweep_begin >= p->sweep_end)
+    return fail(ISING_E_ARG, "window [%d, %d) is not inside [0, %d)", p->sweep_begin, p->sweep_end, p->n_sweeps);
+  if (p->init_spins && p->sweep_begin != 0) return fail(ISING_E_ARG, "init_spins needs sweep_begin == 0");
+  if (!spins_inout) return fail(ISING_E_ARG, "spins_inout is NULL");
+  if (p->replica_offset < 0 || (int64_t)p->replica_offset + p->n_replicas > INT32_MAX)
+    return fail(ISING_E_ARG, "replica_offset out of range");
+  rc = check_device(g);
+  if (rc) return rc;
+  const DeviceInfo dev = device_info(g->device);
+
+  int layout = p->layout;
+  if (layout == ISING_LAYOUT_AUTO) layout = ISING_LAYOUT_I8;
+  if (layout != ISING_LAYOUT_I8) return fail(ISING_E_UNSUPPORTED, "layout %d is not available", p->layout);
+  if (p->replica_offset % 4 != 0) return fail(ISING_E_ARG, "replica_offset must be a multiple of 4");
+  if (ising::sweep_i8_block(g->lat, p->block_threads) <= 0 ||
+      ising::sweep_i8_lds_bytes(g->lat) > dev.lds_per_block)
+    return fail(ISING_E_UNSUPPORTED, "torus of %lld sites does not fit the on-chip sweep kernel",
+                (long long)g->n);
+
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* d_thr = nullptr;
+  bool owned = false;
+  rc = threshold_table(g, p, st, &d_thr, &owned);
+  if (rc) return rc;
+  ising::SweepLaunch s;
+  s.d_thr = d_thr;
+  s.spins = spins_inout;
+  s.cut = cut_out;
+  s.energy = energy_out;
+  s.flips = flips_out;
+  s.stats = (unsigned long long*)p->stats_out;
+  s.seed = p->seed;
+  s.n_replicas = p->n_replicas;
+  s.replica_offset = p->replica_offset;
+  s.t_begin = p->sweep_begin;
+  s.t_end = p->sweep_end;
+  s.init = p->init_spins ? 1 : 0;
+  s.block_threads = p->block_threads;
+  hipError_t e = ising::launch_sweep_i8(g, s, st);
+  if (owned) (void)hipFreeAsync(d_thr, st);
+  if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");
+  return ISING_OK;
+}
+
+int ising_eval_cut(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut_out,
+                   int64_t* energy_out, void* stream) {
+  if (!g) return fail(ISING_E_ARG, "graph is NULL");
+  if (n_replicas < 0 || n_replicas > INT32_MAX) return fail(ISING_E_ARG, "n_replicas out of range");
+  if (n_replicas > 0 && !spins) return fail(ISING_E_ARG, "spins is NULL");
+  int rc = check_device(g);
+  if (rc) return rc;
+  hipError_t e = ising::launch_cut_energy(g, spins, n_replicas, cut_out, energy_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "cut kernel launch");
+  return ISING_OK;
+}
+
+int ising_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, void* stream) {
+  if (m < 0 || m > ((int64_t)1 << 31)) return fail(ISING_E_ARG, "m out of range");
+  if (m > 0 && (!ctr || !out)) return fail(ISING_E_ARG, "ctr or out is NULL");
+  hipError_t e = ising::launch_philox_dump(key, ctr, m, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "philox kernel launch");
+  return ISING_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Exact cut and energy of R states (paper, Section II): for every edge e =
+// (a, b), counted once, cut += w_e [s_a != s_b] (eq. (1)) and
+// H += w_e s_a s_b (eq. (2) with J = -w, h = 0).  One block per replica,
+// integer arithmetic throughout.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "philox.hpp"
+#include "reduce.hpp"
+
+namespace ising {
+namespace {
+
+constexpr int kCutBlock = 256;
+
+template <int NDIM>
+__global__ void __launch_bounds__(kCutBlock) k_cut_energy(Lattice L, const int8_t* w, const int8_t* spins,
+                                                          int64_t* cut, int64_t* energy) {
+  const size_t n = (size_t)L.n;
+  const int8_t* s = spins + (size_t)blockIdx.x * n;
+  const uint32_t Lx = (uint32_t)L.Lx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz;
+  const uint32_t plane = Lx * Ly;
+  int32_t c = 0, h = 0, bad = 0;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)L.n; i += kCutBlock) {
+    const uint32_t line = fdiv(i, L.div_lx);
+    const uint32_t x = i - line * Lx;
+    const uint32_t z = NDIM == 2 ? 0u : fdiv(line, L.div_ly);
+    const uint32_t y = line - z * Ly;
+    const int si = s[i];
+    bad |= (si != 1 && si != -1);
+    uint32_t nb[NDIM];
+    nb[0] = (x + 1u == Lx) ? i + 1u - Lx : i + 1u;
+    nb[1] = (y + 1u == Ly) ? i + Lx - plane : i + Lx;
+    if (NDIM == 3) nb[NDIM - 1] = (z + 1u == Lz) ? i - (Lz - 1u) * plane : i + plane;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+      const int sj = s[nb[d]];
+      const int we = w[(size_t)NDIM * i + d];
+      h += we * si * sj;
+      c += (si != sj) ? we : 0;
+    }
+  }
+  const int64_t ct = block_sum<kCutBlock>((int64_t)c);
+  const int64_t ht = block_sum<kCutBlock>((int64_t)h);
+  const int64_t bt = block_sum<kCutBlock>((int64_t)bad);
+  if (threadIdx.x == 0) {
+    if (cut) cut[blockIdx.x] = bt ? INT64_MIN : ct;
+    if (energy) energy[blockIdx.x] = bt ? INT64_MIN : ht;
+  }
+}
+
+__global__ void k_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const uint32_t* c = ctr + 4 * k;
+  const u32x4 o = philox_lanes(key, c[0], c[1], c[2], c[3]);
+  out[4 * k + 0] = o.v[0];
+  out[4 * k + 1] = o.v[1];
+  out[4 * k + 2] = o.v[2];
+  out[4 * k + 3] = o.v[3];
+}
+
+}  // namespace
+
+hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut,
+                             int64_t* energy, hipStream_t stream) {
+  if (n_replicas == 0) return hipSuccess;
+  if (g->ndim == 2)
+    hipLaunchKernelGGL(k_cut_energy<2>, dim3((unsigned)n_replicas), dim3(kCutBlock), 0, stream, g->lat, g->d_w,
+                       spins, cut, energy);
+  else
+    hipLaunchKernelGGL(k_cut_energy<3>, dim3((unsigned)n_replicas), dim3(kCutBlock), 0, stream, g->lat, g->d_w,
+                       spins, cut, energy);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, hipStream_t stream) {
+  if (m == 0) return hipSuccess;
+  const int block = 256;
+  const int64_t grid = (m + block - 1) / block;
+  hipLaunchKernelGGL(k_philox_dump, dim3((unsigned)grid), dim3(block), 0, stream, key, ctr, m, out);
+  return hipGetLastError();
+}
+
+}  // namespace ising

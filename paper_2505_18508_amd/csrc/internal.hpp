@@ -1,0 +1,65 @@
+// Internal declarations of the library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lattice.hpp"
+
+struct ThrCacheEntry {
+  int32_t schedule, n_sweeps, kmax;
+  double beta0, beta1;
+  uint64_t table_hash;
+  uint32_t* d_thr;  // device [n_sweeps][kmax]
+};
+
+struct ising_graph {
+  int32_t ndim;
+  int32_t dims[3];
+  ising::Lattice lat;
+  int64_t n, n_edges, w_total;
+  int32_t degree;
+  int device;
+  std::vector<int8_t> w_host;  // edge order
+  int8_t* d_w = nullptr;       // device edge weights [n_edges]
+  uint8_t* d_wbits = nullptr;  // device per-site weight sign bits, colour-split order [n]
+  mutable std::mutex mu;
+  mutable std::vector<ThrCacheEntry> thr_cache;
+};
+
+namespace ising {
+
+// Work description of one sweep-kernel launch (device pointers).
+struct SweepLaunch {
+  const uint32_t* d_thr;  // full-schedule threshold table [S][kmax]
+  int8_t* spins;
+  int64_t* cut;
+  int64_t* energy;
+  uint32_t* flips;
+  unsigned long long* stats;
+  uint64_t seed;
+  int32_t n_replicas;
+  int32_t replica_offset;
+  int32_t t_begin, t_end;
+  int32_t init;
+  int32_t block_threads;
+};
+
+hipError_t launch_sweep_i8(const ising_graph* g, const SweepLaunch& s, hipStream_t stream);
+hipError_t launch_sweep_bp32(const ising_graph* g, const SweepLaunch& s, hipStream_t stream);
+hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut,
+                             int64_t* energy, hipStream_t stream);
+hipError_t launch_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, hipStream_t stream);
+
+// LDS bytes one block of each sweep kernel needs for a lattice.
+size_t sweep_i8_lds_bytes(const Lattice& L);
+size_t sweep_bp32_lds_bytes(const Lattice& L);
+// Block size a sweep kernel uses for a requested size (0 = default).
+int sweep_i8_block(const Lattice& L, int requested);
+int sweep_bp32_block(const Lattice& L, int requested);
+
+}  // namespace ising

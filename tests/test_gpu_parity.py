@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle
+on the same seeded inputs.  Spins, cuts, energies, flip counts and Philox
+streams must agree bit for bit (integer work)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+SCHED = {"linear": oracle.SCHED_LINEAR, "geometric": oracle.SCHED_GEOMETRIC, "table": oracle.SCHED_TABLE}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_18508_amd as ising
+
+    ising.lib()
+    return torch.device("cuda:0")
+
+
+def _ising():
+    import paper_2505_18508_amd as ising
+
+    return ising
+
+
+def run_gpu(dims, weight_seed, seed, R, S, begin=0, end=None, schedule="linear", beta0=0.1, beta1=3.0,
+            table=None, spins0=None, layout="auto", block_threads=0, replica_offset=0, weights=None):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph(dims, weight_seed, weights)
+    n = g.n
+    if spins0 is None:
+        spins = torch.zeros((R, n), dtype=torch.int8, device="cuda")
+    else:
+        spins = torch.from_numpy(np.ascontiguousarray(spins0)).cuda()
+    cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+    en = torch.zeros(R, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(R, dtype=torch.int32, device="cuda")
+    ising.run_trials(g, spins, seed, S, begin, end, schedule, beta0, beta1, table, spins0 is None, layout,
+                     cut, en, fl, block_threads, replica_offset)
+    torch.cuda.synchronize()
+    out = (spins.cpu().numpy(), cut.cpu().numpy(), en.cpu().numpy(), fl.cpu().numpy().astype(np.uint32))
+    g.close()
+    return out
+
+
+def run_oracle(dims, weight_seed, seed, R, S, begin=0, end=None, schedule="linear", beta0=0.1, beta1=3.0,
+               table=None, spins0=None, replica_begin=0, weights=None):
+    n = oracle.n_sites(dims)
+    w = oracle.random_weights(weight_seed, len(dims) * n) if weights is None else weights
+    s, fl = oracle.run(dims, w, seed, R, S, begin, end, SCHED[schedule], beta0, beta1, table, spins0,
+                       replica_begin=replica_begin)
+    cut, en = oracle.cut_energy(dims, w, s)
+    return s, cut, en, fl
+
+
+def assert_same(gpu, orc, rows=None):
+    gs, gc, ge, gf = gpu
+    if rows is not None:
+        gs, gc, ge, gf = gs[rows], gc[rows], ge[rows], gf[rows]
+    os_, oc, oe, of = orc
+    assert gs.shape == os_.shape
+    mism = np.nonzero((gs != os_).any(axis=1))[0]
+    assert len(mism) == 0, "replicas differ: %s" % mism[:10]
+    assert (gc == oc).all() and (ge == oe).all()
+    assert (gf == of).all()
+
+
+# --------------------------------------------------------------------------
+def test_philox_stream_matches_oracle(dev):
+    import torch
+
+    rng = np.random.default_rng(1)
+    m = 4096
+    ctr = rng.integers(0, 2**32, size=(m, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:16] = [[i, t, q, tag] for i in range(2) for t in range(2) for q in range(2) for tag in range(2)]
+    key = 0x0123456789ABCDEF
+    c = torch.from_numpy(ctr.view(np.int32)).cuda()
+    out = torch.zeros((m, 4), dtype=torch.int32, device="cuda")
+    _ising().philox_dump(key, c, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    for k in list(range(64)) + list(rng.integers(0, m, size=200)):
+        assert (got[k] == oracle.philox(key, ctr[k])).all(), k
+
+
+def test_c1_full_run_bit_exact(dev):
+    c = inputs.C1
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
+                  beta0=c["beta0"], beta1=c["beta1"])
+    orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
+                     beta0=c["beta0"], beta1=c["beta1"])
+    assert_same(gpu, orc)
+
+
+def test_c2_first_200_sweeps_sampled_replicas(dev):
+    """All 1,024 replicas on the GPU for sweeps [0, 200) of the 10,000-sweep
+    schedule; the oracle recomputes 24 of them (first, middle, last quads)."""
+    c = inputs.C2
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"])
+    for start in (0, 4, 508, 512, 1016, 1020):
+        orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, 200, c["schedule"], c["beta0"],
+                         c["beta1"], replica_begin=start)
+        assert_same(gpu, orc, rows=slice(start, start + 4))
+
+
+def test_c4_shape_short_window_sampled(dev):
+    """The 20,000-spin torus with 8,192 replicas (full launch shape), 30 sweeps."""
+    c = inputs.C4
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 30, c["schedule"], c["beta0"], c["beta1"])
+    for start in (0, 4096, 8188):
+        orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, 30, c["schedule"], c["beta0"],
+                         c["beta1"], replica_begin=start)
+        assert_same(gpu, orc, rows=slice(start, start + 4))
+
+
+@pytest.mark.parametrize("dims,R", [([2, 2], 5), ([2, 4], 3), ([4, 2], 8), ([4, 6], 13), ([6, 8], 1), ([2, 6], 7),
+                                    ([2, 2, 2], 6), ([4, 4, 6], 9), ([6, 8, 10], 4), ([2, 4, 2], 2),
+                                    ([34, 18], 11), ([10, 1000], 3)])
+def test_small_and_ragged_tori(dev, dims, R):
+    gpu = run_gpu(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0)
+    orc = run_oracle(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0)
+    assert_same(gpu, orc)
+
+
+def test_3d_degree6_torus(dev):
+    dims = [16, 16, 16]
+    gpu = run_gpu(dims, 643, 9, 12, 120, schedule="geometric", beta0=0.05, beta1=4.0)
+    orc = run_oracle(dims, 643, 9, 12, 120, schedule="geometric", beta0=0.05, beta1=4.0)
+    assert_same(gpu, orc)
+
+
+def test_given_spins_and_weights_and_table_schedule(dev):
+    dims = [20, 30]
+    n = 600
+    w = inputs.random_weights(5, 2 * n)
+    s0 = inputs.random_spins(6, 10, n)
+    table = np.linspace(0.3, 2.5, 150)
+    gpu = run_gpu(dims, 0, 77, 10, 150, schedule="table", table=table, spins0=s0, weights=w)
+    orc = run_oracle(dims, 0, 77, 10, 150, schedule="table", table=table, spins0=s0, weights=w)
+    assert_same(gpu, orc)
+
+
+def test_window_resume_equals_single_run(dev):
+    dims = [40, 50]
+    full = run_gpu(dims, 3, 8, 8, 400, schedule="geometric", beta0=0.05, beta1=4.0)
+    a = run_gpu(dims, 3, 8, 8, 400, 0, 170, schedule="geometric", beta0=0.05, beta1=4.0)
+    b = run_gpu(dims, 3, 8, 8, 400, 170, 400, schedule="geometric", beta0=0.05, beta1=4.0, spins0=a[0])
+    assert (b[0] == full[0]).all() and (b[1] == full[1]).all()
+    assert (a[3] + b[3] == full[3]).all()
+
+
+def test_replica_offset_selects_streams(dev):
+    dims = [10, 12]
+    full = run_gpu(dims, 3, 8, 24, 100)
+    part = run_gpu(dims, 3, 8, 8, 100, replica_offset=12)
+    assert (part[0] == full[0][12:20]).all()
+
+
+@pytest.mark.parametrize("bt", [100, 300, 512, 1000])
+def test_block_size_does_not_change_results(dev, bt):
+    c = inputs.C1
+    ref = run_gpu(c["dims"], c["weight_seed"], c["seed"], 8, 200, schedule="linear")
+    got = run_gpu(c["dims"], c["weight_seed"], c["seed"], 8, 200, schedule="linear", block_threads=bt)
+    assert (ref[0] == got[0]).all() and (ref[3] == got[3]).all()
+
+
+def test_largest_on_chip_torus(dev):
+    dims = [200, 204]  # 40,800 sites: 163,200 B of LDS per block
+    gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
+    orc = run_oracle(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
+    assert_same(gpu, orc)
+
+
+def test_too_large_torus_is_rejected(dev):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph([256, 256], 1)
+    s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
+    with pytest.raises(ising.IsingError) as e:
+        ising.run_trials(g, s, 1, 10, layout="i8")
+    assert e.value.code == ising.E_UNSUPPORTED
+
+
+def test_invalid_input_spins_flagged(dev):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph([6, 8], 2)
+    s0 = inputs.random_spins(1, 8, g.n)
+    s0[3, 7] = 0
+    s0[5, 0] = 3
+    s = torch.from_numpy(s0).cuda()
+    cut = torch.zeros(8, dtype=torch.int64, device="cuda")
+    en = torch.zeros(8, dtype=torch.int64, device="cuda")
+    ising.run_trials(g, s, 1, 10, init_spins=False, cut=cut, energy=en)
+    torch.cuda.synchronize()
+    c = cut.cpu().numpy()
+    assert c[3] == ising.INVALID_VALUE and c[5] == ising.INVALID_VALUE
+    assert (np.delete(c, [3, 5]) != ising.INVALID_VALUE).all()
+
+
+def test_argument_errors(dev):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph([6, 8], 2)
+    s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
+    cases = [dict(n_sweeps=10, sweep_begin=5, sweep_end=5), dict(n_sweeps=10, sweep_begin=0, sweep_end=11),
+             dict(n_sweeps=10, sweep_begin=2, sweep_end=5, init_spins=True), dict(n_sweeps=10, schedule="geometric", beta0=0.0),
+             dict(n_sweeps=10, replica_offset=2)]
+    for kw in cases:
+        n_sweeps = kw.pop("n_sweeps")
+        with pytest.raises(ising.IsingError) as e:
+            ising.run_trials(g, s, 1, n_sweeps, **kw)
+        assert e.value.code == ising.E_ARG, kw
+
+
+# --------------------------------------------------------------------------
+# eval_cut
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dims", [[50, 100], [2, 2], [4, 6], [100, 200], [6, 4, 8], [64, 64, 64]])
+def test_eval_cut_matches_oracle(dev, dims):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph(dims, 11)
+    n = g.n
+    R = 9
+    s0 = inputs.random_spins(2, R, n)
+    s0[1] = 1
+    s0[2] = -1
+    s0[3] = np.where(oracle.colours(dims) == 0, 1, -1) if n <= 50000 else s0[3]
+    s = torch.from_numpy(s0).cuda()
+    cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+    en = torch.zeros(R, dtype=torch.int64, device="cuda")
+    ising.eval_cut(g, s, cut, en)
+    torch.cuda.synchronize()
+    w = oracle.random_weights(11, len(dims) * n)
+    oc, oe = oracle.cut_energy(dims, w, s0)
+    assert (cut.cpu().numpy() == oc).all() and (en.cpu().numpy() == oe).all()
+    assert (g.weights() == w).all()
+
+
+def test_eval_cut_flags_invalid_values(dev):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph([4, 6], 1)
+    s0 = inputs.random_spins(3, 4, g.n)
+    s0[2, 5] = 0
+    s = torch.from_numpy(s0).cuda()
+    cut = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ising.eval_cut(g, s, cut, None)
+    torch.cuda.synchronize()
+    c = cut.cpu().numpy()
+    assert c[2] == ising.INVALID_VALUE and (np.delete(c, 2) != ising.INVALID_VALUE).all()
+
+
+def test_eval_cut_empty(dev):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph([4, 6], 1)
+    s = torch.zeros((0, g.n), dtype=torch.int8, device="cuda")
+    ising.eval_cut(g, s, None, None)
+    torch.cuda.synchronize()

@@ -1,0 +1,92 @@
+"""CPU tests of the product's host side: the C ABI loads and exports every
+declared symbol, host-only entry points agree with the oracle, argument
+errors are reported.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2505_18508_amd as ising
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ising.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ising_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert "ising_run_trials" in names and "ising_eval_cut" in names and "ising_create_graph" in names
+    L = ising.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(ising.EXPORTED)
+
+
+@pytest.mark.parametrize("sched,b0,b1,S", [("linear", 0.1, 3.0, 1000), ("geometric", 0.05, 4.0, 10000),
+                                           ("linear", 0.0, 0.0, 7), ("geometric", 0.3, 0.3, 1),
+                                           ("linear", 2.5, 0.2, 333), ("geometric", 4.0, 0.05, 2)])
+@pytest.mark.parametrize("degree", [4, 6])
+def test_thresholds_match_oracle_bit_for_bit(sched, b0, b1, S, degree):
+    lib_t = ising.thresholds(S, sched, b0, b1, degree=degree)
+    code = oracle.SCHED_LINEAR if sched == "linear" else oracle.SCHED_GEOMETRIC
+    orc_t = oracle.thresholds(code, b0, b1, S, degree)
+    assert lib_t.dtype == np.uint32 and (lib_t == orc_t).all()
+
+
+def test_table_schedule_thresholds_match_oracle():
+    rng = np.random.default_rng(3)
+    table = rng.uniform(0.0, 5.0, size=500)
+    table[:3] = [0.0, 1e-300, 100.0]
+    lib_t = ising.thresholds(500, "table", beta_table=table, degree=6)
+    orc_t = oracle.thresholds(oracle.SCHED_TABLE, 0, 0, 500, 6, table=table)
+    assert (lib_t == orc_t).all()
+
+
+@pytest.mark.parametrize("dims,seed", [([2, 2], 1), ([50, 100], 1), ([100, 100], 2), ([100, 200], 81),
+                                       ([2, 4, 6], 5), ([8, 8, 8], 643), ([6, 10], 2**63 + 11)])
+def test_generated_weights_match_oracle(dims, seed):
+    w = ising.generate_weights(dims, seed)
+    ne = len(dims) * int(np.prod(dims))
+    assert (w == oracle.random_weights(seed, ne)).all()
+
+
+def test_host_argument_errors():
+    with pytest.raises(ising.IsingError) as e:
+        ising.generate_weights([3, 4], 1)
+    assert e.value.code == ising.E_TOPOLOGY
+    with pytest.raises(ising.IsingError) as e:
+        ising.generate_weights([4, 4, 4, 4], 1)
+    assert e.value.code == ising.E_TOPOLOGY
+    with pytest.raises(ising.IsingError) as e:
+        ising.generate_weights([0, 4], 1)
+    assert e.value.code == ising.E_TOPOLOGY
+    with pytest.raises(ising.IsingError) as e:
+        ising.thresholds(10, "geometric", 0.0, 1.0)
+    assert e.value.code == ising.E_ARG
+    with pytest.raises(ising.IsingError) as e:
+        ising.thresholds(10, "linear", -0.5, 1.0)
+    assert e.value.code == ising.E_ARG
+    with pytest.raises(ising.IsingError) as e:
+        ising.thresholds(3, "table", beta_table=[0.1, float("nan"), 0.3])
+    assert e.value.code == ising.E_ARG
+    with pytest.raises(ising.IsingError) as e:
+        ising.thresholds(0, "linear", 0.1, 1.0)
+    assert e.value.code == ising.E_ARG
+    p, keep = ising.make_params(1, 1, 10)
+    p.struct_size = 8
+    rc = ising.lib().ising_thresholds(ctypes.byref(p), 4, ctypes.c_void_p(np.zeros(40, np.uint32).ctypes.data))
+    assert rc == ising.E_ARG
+    assert b"struct_size" in ising.lib().ising_last_error()
+    # graph creation rejects odd tori before touching the device
+    h = ctypes.c_void_p()
+    d = np.array([5, 4], np.int32)
+    assert ising.lib().ising_create_graph(2, d.ctypes.data, 1, None, ctypes.byref(h)) == ising.E_TOPOLOGY
+    assert ising.lib().ising_create_graph(2, None, 1, None, ctypes.byref(h)) == ising.E_ARG
+    ising.lib().ising_destroy_graph(None)  # NULL-safe
