@@ -31,6 +31,7 @@ namespace {
 
 constexpr int kMaxBlock = 1024;
 constexpr int kExtraWords = 16;  // [0,4) flips, 4 invalid flags, [8,12) energy sums, 12-13 stats
+constexpr int kLut = 144;        // threshold table entries: (spin bit << 7) | field, field <= 12
 
 struct I8Args {
   Lattice lat;
@@ -175,65 +176,110 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
   __syncthreads();
 
   // ---- the window of sweeps -----------------------------------------------
+  // Per-sweep threshold table in LDS, double-buffered: entry (spin bit << 7 |
+  // field byte) holds T_k(t) of that state when its dE = 4k > 0, else 0 (a
+  // dE <= 0 state flips without a draw).  Sweep t+1's table is written during
+  // sweep t's first half; two barriers separate it from its first reader.
+  uint32_t* lut = extra + kExtraWords;
+  auto fill_lut = [&](uint32_t* dst, int t) {
+    const uint32_t* tr = a.thr + (size_t)t * NDIM;
+    for (int idx = tid; idx < kLut; idx += B) {
+      const uint32_t fb = (uint32_t)idx & 0xFu;
+      uint32_t v = 0u;
+      // only reachable states: weight bits clear, field even and <= 2 deg
+      if ((idx & 0x70) == 0 && (fb & 1u) == 0u && fb <= 2u * DEG) {
+        const int g = (idx & 0x80) ? (int)fb : 2 * DEG - (int)fb;  // s f + deg, even, 0..2 deg
+        const int k = (DEG - g) / 2;                                 // dE = 4k
+        if (k >= 1 && k <= NDIM) v = tr[k - 1];
+      }
+      dst[idx] = v;
+    }
+  };
+  fill_lut(lut + (a.t_begin & 1) * kLut, a.t_begin);
+  __syncthreads();
+
+  // per-thread neighbour offsets (word index deltas, modulo 2^32)
+  const uint32_t d_up = m_up - m, d_dn = m_dn - m;
+  const uint32_t row = hx, plane = hx * Ly;
+  const uint32_t dyp_wrap = row - plane, dym_wrap = plane - row;
+  const uint32_t Lz = (uint32_t)L.Lz;
+  const uint32_t dzp_wrap = plane - plane * Lz, dzm_wrap = plane * Lz - plane;
+  const uint32_t own_step = lp * hx;
+  const uint32_t ci_step = lp * (uint32_t)L.Lx;
+
   uint32_t fl0 = 0u, fl1 = 0u, fl2 = 0u, fl3 = 0u;
   uint32_t n_blocks = 0u, n_draws = 0u;  // RNG statistics (STATS only)
   const uint32_t valid_mask = (1u << nvalid) - 1u;
-  constexpr uint32_t kTwoDeg = (uint32_t)(2 * DEG) * kOnes;
-  constexpr uint32_t kAccBias = (uint32_t)(0x80 - DEG) * kOnes;
+  constexpr uint32_t kGeBias = (uint32_t)(0x80 - DEG) * kOnes;  // + fb: bit 7 iff fb >= deg
+  constexpr uint32_t kLeBias = (uint32_t)(0x80 + DEG) * kOnes;  // - fb: bit 7 iff fb <= deg
   for (int t = a.t_begin; t < a.t_end; ++t) {
-    const uint32_t* tr = a.thr + (size_t)t * NDIM;
-    const uint32_t t1 = tr[0], t2 = tr[1], t3 = NDIM == 3 ? tr[2] : 0u;
-    uint32_t fc_lo = 0u, fc_hi = 0u;  // packed 16-bit flip counters
+    const uint32_t* cur = lut + (t & 1) * kLut;
+    uint32_t fc_lo = 0u, fc_hi = 0u;  // flips, packed 16-bit lanes (bytes 0,2 / 1,3)
     for (int p = 0; p < 2; ++p) {
+      if (p == 0 && t + 1 < a.t_end) fill_lut(lut + ((t + 1) & 1) * kLut, t + 1);
+      uint32_t fc8 = 0u;  // flips this half-sweep, packed bytes
       if (active) {
+        const uint32_t other = (uint32_t)(1 - 2 * p) * (uint32_t)L.half;
+        uint32_t own = (uint32_t)p * (uint32_t)L.half + line0 * hx + m;
+        uint32_t ci0 = line0 * (uint32_t)L.Lx + 2u * m;
         uint32_t y = y0, z = z0;
         for (uint32_t line = line0; line < (uint32_t)L.lines; line += lp) {
-          const SiteGeom<NDIM> s = site_geom<NDIM>(L, p, line, y, z, m, m_up, m_dn);
+          const uint32_t o = (p + y + z) & 1u;
+          const uint32_t base = own + other;
+          uint32_t nb[DEG];
+          nb[0] = base + (o ? d_up : 0u);
+          nb[1] = base + (o ? 0u : d_dn);
+          nb[2] = base + (y + 1u == Ly ? dyp_wrap : row);
+          nb[3] = base + (y == 0u ? dym_wrap : 0u - row);
+          if (NDIM == 3) {
+            nb[DEG - 2] = base + (z + 1u == Lz ? dzp_wrap : plane);
+            nb[DEG - 1] = base + (z == 0u ? dzm_wrap : 0u - plane);
+          }
+          const uint32_t ci = ci0 + o;
+          const uint32_t w = lds[own];
+          // dE <= 0 per byte: fb >= deg for spin +1, fb <= deg for spin -1
+          const uint32_t fb = w & 0x0F0F0F0Fu;
+          const uint32_t ge = fb + kGeBias, le = kLeBias - fb;
+          const uint32_t acc = ((w & ge) | (~w & le)) & 0x80808080u;
+          uint32_t F = acc >> 7;
+          const uint32_t T0 = cur[w & 0x8Fu];
+          const uint32_t T1 = cur[(w >> 8) & 0x8Fu];
+          const uint32_t T2 = cur[(w >> 16) & 0x8Fu];
+          const uint32_t T3 = cur[(w >> 24) & 0x8Fu];
+          const bool need = (T0 | T1 | T2 | T3) != 0u;
+          if (STATS && need) {
+            const uint32_t nm = (T0 ? 1u : 0u) | (T1 ? 2u : 0u) | (T2 ? 4u : 0u) | (T3 ? 8u : 0u);
+            n_blocks += 1u;
+            n_draws += __popc(nm & valid_mask);
+          }
+          if (need) {
+            const u32x4 u = philox_lane_c0(a.seed, ci, (uint32_t)t, quad, kTagMetropolis);
+            const uint32_t m4 = (u.v[0] < T0 ? 1u : 0u) | (u.v[1] < T1 ? 2u : 0u) | (u.v[2] < T2 ? 4u : 0u) |
+                                (u.v[3] < T3 ? 8u : 0u);
+            F |= (m4 * 0x00204081u) & kOnes;  // bit b -> bit 8b
+          }
+          if (F) {
+            lds[own] = w ^ (F << 7);
+            // field change of a neighbour over a +1 edge: -2 s_i(old) per flipped byte
+            const uint32_t up = (w >> 7) & F;  // flipped bytes whose old spin was +1
+            const uint32_t D = 2u * (F - 2u * up);
+            const uint32_t wb = ((w >> 4) & 7u) | ((w >> 9) & 0x38u);
+#pragma unroll
+            for (int d = 0; d < DEG; ++d) atomicAdd(&lds[nb[d]], ((wb >> d) & 1u) ? 0u - D : D);
+            fc8 += F;
+          }
+          own += own_step;
+          ci0 += ci_step;
           y += lp_y;
           z += lp_z;
           if (y >= Ly) {
             y -= Ly;
             z += 1u;
           }
-          const uint32_t w = lds[s.own];
-          const uint32_t fb = w & 0x0F0F0F0Fu;
-          const uint32_t spm = (w >> 7) & kOnes;
-          const uint32_t negm = (spm ^ kOnes) * 0xFFu;
-          const uint32_t g = (fb & ~negm) | ((kTwoDeg - fb) & negm);  // s f + deg per byte
-          const uint32_t acc = (g + kAccBias) & 0x80808080u;           // dE <= 0
-          uint32_t F = acc >> 7;
-          if (acc != 0x80808080u) {
-            uint32_t tb[4];
-            bool need = false;
-            uint32_t need_mask = 0u;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const uint32_t gb = (g >> (8 * b)) & 0xFFu;
-              tb[b] = ((acc >> (8 * b + 7)) & 1u) ? 0u : thr_for_g<NDIM>(gb, t1, t2, t3);
-              need |= tb[b] != 0u;
-              if (STATS) need_mask |= (tb[b] != 0u ? 1u : 0u) << b;
-            }
-            if (STATS && need) {
-              n_blocks += 1u;
-              n_draws += __popc(need_mask & valid_mask);
-            }
-            if (need) {
-              const u32x4 u = philox_lane_c0(a.seed, s.ci, (uint32_t)t, quad, kTagMetropolis);
-#pragma unroll
-              for (int b = 0; b < 4; ++b) F |= (u.v[b] < tb[b] ? 1u : 0u) << (8 * b);
-            }
-          }
-          if (F) {
-            lds[s.own] = w ^ (F << 7);
-            const uint32_t D = 2u * ((F & ~spm) - (F & spm));
-            const uint32_t wb = ((w >> 4) & 7u) | ((w >> 9) & 0x38u);
-#pragma unroll
-            for (int d = 0; d < DEG; ++d) atomicAdd(&lds[s.nb[d]], ((wb >> d) & 1u) ? 0u - D : D);
-            fc_lo += F & 0x00FF00FFu;
-            fc_hi += (F >> 8) & 0x00FF00FFu;
-          }
         }
       }
+      fc_lo += fc8 & 0x00FF00FFu;
+      fc_hi += (fc8 >> 8) & 0x00FF00FFu;
       __syncthreads();
     }
     fl0 += fc_lo & 0xFFFFu;
@@ -243,6 +289,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
   }
 
   // ---- energy from the maintained fields ----------------------------------
+  constexpr uint32_t kTwoDeg = (uint32_t)(2 * DEG) * kOnes;
   uint32_t e0 = 0u, e1 = 0u, e2 = 0u, e3 = 0u;
   if (active) {
     for (int p = 0; p < 2; ++p) {
@@ -300,7 +347,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
 
 }  // namespace
 
-size_t sweep_i8_lds_bytes(const Lattice& L) { return (size_t)L.n * 4u + kExtraWords * 4u; }
+size_t sweep_i8_lds_bytes(const Lattice& L) { return ((size_t)L.n + kExtraWords + 2 * kLut) * 4u; }
 
 int sweep_i8_block(const Lattice& L, int requested) {
   if (L.hx > kMaxBlock) return 0;
@@ -312,6 +359,11 @@ int sweep_i8_block(const Lattice& L, int requested) {
     if (lp < 1) lp = 1;
     if (lp > max_lp) lp = max_lp;
   }
+  // a thread visits ceil(lines / lp) sites per half-sweep; flip counters are
+  // packed bytes, so keep that <= 255
+  const int min_lp = (L.lines + 254) / 255;
+  if (lp < min_lp) lp = min_lp;
+  if (lp * L.hx > kMaxBlock) return 0;
   return lp * L.hx;
 }
 

@@ -173,7 +173,7 @@ def test_block_size_does_not_change_results(dev, bt):
 
 
 def test_largest_on_chip_torus(dev):
-    dims = [200, 204]  # 40,800 sites: 163,200 B of LDS per block
+    dims = [200, 202]  # 40,400 sites: 162,816 B of LDS per block
     gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
     orc = run_oracle(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
