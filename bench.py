@@ -22,8 +22,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05,
-                beta1=4.0)
+WORKLOADS = {
+    "c2": dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05, beta1=4.0,
+               name="2-D torus 100x100 (10,000 spins, weight seed 2), 1,024 replicas, 10,000 sweeps, "
+                    "geometric beta 0.05->4.0, run seed 102"),
+    "c4": dict(dims=[100, 200], weight_seed=81, seed=201, R=8192, S=40000, schedule="geometric", beta0=0.05, beta1=4.0,
+               name="2-D torus 100x200 (20,000 spins, weight seed 81), 8,192 replicas, 40,000 sweeps, "
+                    "geometric beta 0.05->4.0, run seed 201"),
+}
+WORKLOAD = WORKLOADS["c2"]
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU issue
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # algorithmic VALU lane-ops: one Philox4x32-10 word per attempt that needs a
@@ -52,9 +59,10 @@ def cpu_baseline(budget_s):
 
     import oracle
 
-    w = oracle.random_weights(WORKLOAD["weight_seed"], 2 * 100 * 100)
+    n = WORKLOAD["dims"][0] * WORKLOAD["dims"][1]
+    w = oracle.random_weights(WORKLOAD["weight_seed"], 2 * n)
     cores = min(os.cpu_count() or 1, 16)
-    S, n = WORKLOAD["S"], 10000
+    S = WORKLOAD["S"]
 
     t0 = time.perf_counter()
     done = []
@@ -63,14 +71,14 @@ def cpu_baseline(budget_s):
         futs = []
         r = 0
         while r < cores:
-            futs.append(ex.submit(_oracle_one, r, w))
+            futs.append(ex.submit(_oracle_one, r, w, WORKLOAD))
             r += 1
         while futs:
             f = futs.pop(0)
             rr, spins = f.result()
             done.append((rr, spins))
             if time.perf_counter() - t0 < budget_s and r < WORKLOAD["R"]:
-                futs.append(ex.submit(_oracle_one, r, w))
+                futs.append(ex.submit(_oracle_one, r, w, WORKLOAD))
                 r += 1
     elapsed = time.perf_counter() - t0
     attempts = len(done) * n * S
@@ -78,11 +86,11 @@ def cpu_baseline(budget_s):
             "sample": "%d replicas x full %d-sweep schedule of the same workload (%.1f s)" % (len(done), S, elapsed)}, done
 
 
-def _oracle_one(r, w):
+def _oracle_one(r, w, wl):
     import oracle
 
-    s, _ = oracle.run(WORKLOAD["dims"], w, WORKLOAD["seed"], 1, WORKLOAD["S"], schedule=oracle.SCHED_GEOMETRIC,
-                      beta0=WORKLOAD["beta0"], beta1=WORKLOAD["beta1"], replica_begin=r)
+    s, _ = oracle.run(wl["dims"], w, wl["seed"], 1, wl["S"], schedule=oracle.SCHED_GEOMETRIC,
+                      beta0=wl["beta0"], beta1=wl["beta1"], replica_begin=r)
     return r, s[0]
 
 
@@ -95,7 +103,10 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
     args = ap.parse_args()
+    global WORKLOAD
+    WORKLOAD = WORKLOADS[args.workload]
     if args.gpus != 1:
         print("bench.py measures one GPU only: the replica-parallel path has no cross-GPU step to time "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -120,6 +131,11 @@ def main():
     energy = torch.zeros(R, dtype=torch.int64, device=dev)
     flips = torch.zeros(R, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    groups = (R + 31) // 32
+    layout = args.layout
+    if layout == "auto":
+        layout = "bp32" if groups >= torch.cuda.get_device_properties(dev).multi_processor_count else "i8"
+    kernel_name = "k_sweep_bp32" if layout == "bp32" else "k_sweep_i8"
 
     def launch(stats=None):
         ising.run_trials(g, spins, W["seed"], S, 0, S, W["schedule"], W["beta0"], W["beta1"], None, True,
@@ -173,14 +189,12 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "2-D torus 100x100 (10,000 spins, weight seed 2), 1,024 replicas, 10,000 sweeps, "
-                               "geometric beta 0.05->4.0, run seed 102",
-                   "layout": args.layout, "replicas": R, "sweeps": S, "spins": n},
+        "config": {"workload": W["name"], "layout": args.layout, "replicas": R, "sweeps": S, "spins": n},
         "kernel_attempts_per_s": attempts / avg_kernel_s,
         "kernel_ms": avg_kernel_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None,
-                     "kernel": "k_sweep_i8", "philox_blocks": blocks, "draws": draws,
+                     "kernel": kernel_name, "philox_blocks": blocks, "draws": draws,
                      "draw_fraction": draws / attempts},
         "readout": {"best_cut": results[-1][0], "target": target, "P_s": p_s, "r": r, "STT_sweeps": S * r},
     }

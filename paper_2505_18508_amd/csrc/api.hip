@@ -350,14 +350,23 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
   if (rc) return rc;
   const DeviceInfo dev = device_info(g->device);
 
-  int layout = p->layout;
-  if (layout == ISING_LAYOUT_AUTO) layout = ISING_LAYOUT_I8;
-  if (layout != ISING_LAYOUT_I8) return fail(ISING_E_UNSUPPORTED, "layout %d is not available", p->layout);
   if (p->replica_offset % 4 != 0) return fail(ISING_E_ARG, "replica_offset must be a multiple of 4");
-  if (ising::sweep_i8_block(g->lat, p->block_threads) <= 0 ||
-      ising::sweep_i8_lds_bytes(g->lat) > dev.lds_per_block)
-    return fail(ISING_E_UNSUPPORTED, "torus of %lld sites does not fit the on-chip sweep kernel",
-                (long long)g->n);
+  const bool i8_fits = ising::sweep_i8_block(g->lat, p->block_threads) > 0 &&
+                       ising::sweep_i8_lds_bytes(g->lat) <= dev.lds_per_block;
+  const bool bp_fits = ising::sweep_bp32_block(g->lat, p->block_threads) > 0 &&
+                       ising::sweep_bp32_lds_bytes(g->lat) <= dev.lds_per_block;
+  int layout = p->layout;
+  if (layout == ISING_LAYOUT_AUTO) {
+    // 32 replicas per block wins per attempt, but only fills the chip with at
+    // least one group per compute unit
+    const int64_t groups = ((int64_t)p->n_replicas + 31) / 32;
+    layout = (bp_fits && (groups >= dev.cus || !i8_fits)) ? ISING_LAYOUT_BP32 : ISING_LAYOUT_I8;
+  }
+  if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32)
+    return fail(ISING_E_ARG, "unknown layout %d", p->layout);
+  if ((layout == ISING_LAYOUT_I8 && !i8_fits) || (layout == ISING_LAYOUT_BP32 && !bp_fits))
+    return fail(ISING_E_UNSUPPORTED, "torus of %lld sites does not fit the on-chip sweep kernel of layout %d",
+                (long long)g->n, layout);
 
   hipStream_t st = (hipStream_t)stream;
   uint32_t* d_thr = nullptr;
@@ -378,7 +387,7 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
   s.t_end = p->sweep_end;
   s.init = p->init_spins ? 1 : 0;
   s.block_threads = p->block_threads;
-  hipError_t e = ising::launch_sweep_i8(g, s, st);
+  hipError_t e = layout == ISING_LAYOUT_BP32 ? ising::launch_sweep_bp32(g, s, st) : ising::launch_sweep_i8(g, s, st);
   if (owned) (void)hipFreeAsync(d_thr, st);
   if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");
   return ISING_OK;

@@ -30,7 +30,7 @@ namespace ising {
 namespace {
 
 constexpr int kMaxBlock = 1024;
-constexpr int kExtraWords = 16;  // [0,4) flips, 4 invalid flags, [8,12) energy sums, 12-13 stats
+constexpr int kExtraWords = 16;  // [0,4) flips, 4 invalid flags, [8,12) energy sums
 constexpr int kLut = 144;        // threshold table entries: (spin bit << 7) | field, field <= 12
 
 struct I8Args {
@@ -313,16 +313,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
     atomicAdd(&extra[9], e1);
     atomicAdd(&extra[10], e2);
     atomicAdd(&extra[11], e3);
-    if (STATS) {
-      atomicAdd(&extra[12], n_blocks);
-      atomicAdd(&extra[13], n_draws);
+    // per-thread totals go straight to the 64-bit outputs (a block's total can
+    // exceed 32 bits)
+    if (STATS && (n_blocks | n_draws)) {
+      atomicAdd(&a.stats[0], (unsigned long long)n_blocks);
+      atomicAdd(&a.stats[1], (unsigned long long)n_draws);
     }
   }
   __syncthreads();
-  if (STATS && tid == 0) {
-    atomicAdd(&a.stats[0], (unsigned long long)extra[12]);
-    atomicAdd(&a.stats[1], (unsigned long long)extra[13]);
-  }
 
   // ---- state out ----------------------------------------------------------
   for (uint32_t i = tid; i < (uint32_t)L.n; i += B) {

@@ -10,6 +10,7 @@ from tests import inputs
 pytestmark = pytest.mark.gpu
 
 SCHED = {"linear": oracle.SCHED_LINEAR, "geometric": oracle.SCHED_GEOMETRIC, "table": oracle.SCHED_TABLE}
+LAYOUTS = ["i8", "bp32"]
 
 
 @pytest.fixture(scope="module")
@@ -91,30 +92,47 @@ def test_philox_stream_matches_oracle(dev):
         assert (got[k] == oracle.philox(key, ctr[k])).all(), k
 
 
-def test_c1_full_run_bit_exact(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_c1_full_run_bit_exact(dev, layout):
     c = inputs.C1
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
-                  beta0=c["beta0"], beta1=c["beta1"])
+                  beta0=c["beta0"], beta1=c["beta1"], layout=layout)
     orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
                      beta0=c["beta0"], beta1=c["beta1"])
     assert_same(gpu, orc)
 
 
-def test_c2_first_200_sweeps_sampled_replicas(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_c2_first_200_sweeps_sampled_replicas(dev, layout):
     """All 1,024 replicas on the GPU for sweeps [0, 200) of the 10,000-sweep
     schedule; the oracle recomputes 24 of them (first, middle, last quads)."""
     c = inputs.C2
-    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"])
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
+                  layout=layout)
     for start in (0, 4, 508, 512, 1016, 1020):
         orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, 200, c["schedule"], c["beta0"],
                          c["beta1"], replica_begin=start)
         assert_same(gpu, orc, rows=slice(start, start + 4))
 
 
-def test_c4_shape_short_window_sampled(dev):
+def test_c2_layouts_agree_on_every_replica(dev):
+    """i8 and bp32 packings give identical spins, cuts, energies and flip
+    counts on all 1,024 replicas of sweeps [0, 200)."""
+    c = inputs.C2
+    a = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
+                layout="i8")
+    b = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
+                layout="bp32")
+    for x, y in zip(a, b):
+        assert (x == y).all()
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_c4_shape_short_window_sampled(dev, layout):
     """The 20,000-spin torus with 8,192 replicas (full launch shape), 30 sweeps."""
     c = inputs.C4
-    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 30, c["schedule"], c["beta0"], c["beta1"])
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 30, c["schedule"], c["beta0"], c["beta1"],
+                  layout=layout)
     for start in (0, 4096, 8188):
         orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, 30, c["schedule"], c["beta0"],
                          c["beta1"], replica_begin=start)
@@ -123,58 +141,68 @@ def test_c4_shape_short_window_sampled(dev):
 
 @pytest.mark.parametrize("dims,R", [([2, 2], 5), ([2, 4], 3), ([4, 2], 8), ([4, 6], 13), ([6, 8], 1), ([2, 6], 7),
                                     ([2, 2, 2], 6), ([4, 4, 6], 9), ([6, 8, 10], 4), ([2, 4, 2], 2),
-                                    ([34, 18], 11), ([10, 1000], 3)])
-def test_small_and_ragged_tori(dev, dims, R):
-    gpu = run_gpu(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0)
+                                    ([34, 18], 11), ([10, 1000], 3), ([6, 4], 37), ([8, 6, 4], 33)])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_small_and_ragged_tori(dev, dims, R, layout):
+    gpu = run_gpu(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
     orc = run_oracle(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
 
 
-def test_3d_degree6_torus(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_3d_degree6_torus(dev, layout):
     dims = [16, 16, 16]
-    gpu = run_gpu(dims, 643, 9, 12, 120, schedule="geometric", beta0=0.05, beta1=4.0)
-    orc = run_oracle(dims, 643, 9, 12, 120, schedule="geometric", beta0=0.05, beta1=4.0)
+    gpu = run_gpu(dims, 643, 9, 40, 120, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
+    orc = run_oracle(dims, 643, 9, 40, 120, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
 
 
-def test_given_spins_and_weights_and_table_schedule(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_given_spins_and_weights_and_table_schedule(dev, layout):
     dims = [20, 30]
     n = 600
     w = inputs.random_weights(5, 2 * n)
-    s0 = inputs.random_spins(6, 10, n)
+    s0 = inputs.random_spins(6, 42, n)
     table = np.linspace(0.3, 2.5, 150)
-    gpu = run_gpu(dims, 0, 77, 10, 150, schedule="table", table=table, spins0=s0, weights=w)
-    orc = run_oracle(dims, 0, 77, 10, 150, schedule="table", table=table, spins0=s0, weights=w)
+    table[:5] = 0.0  # beta = 0: every proposal accepted except with probability 2^-32
+    gpu = run_gpu(dims, 0, 77, 42, 150, schedule="table", table=table, spins0=s0, weights=w, layout=layout)
+    orc = run_oracle(dims, 0, 77, 42, 150, schedule="table", table=table, spins0=s0, weights=w)
     assert_same(gpu, orc)
 
 
-def test_window_resume_equals_single_run(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_window_resume_equals_single_run(dev, layout):
     dims = [40, 50]
-    full = run_gpu(dims, 3, 8, 8, 400, schedule="geometric", beta0=0.05, beta1=4.0)
-    a = run_gpu(dims, 3, 8, 8, 400, 0, 170, schedule="geometric", beta0=0.05, beta1=4.0)
-    b = run_gpu(dims, 3, 8, 8, 400, 170, 400, schedule="geometric", beta0=0.05, beta1=4.0, spins0=a[0])
+    full = run_gpu(dims, 3, 8, 40, 400, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
+    a = run_gpu(dims, 3, 8, 40, 400, 0, 170, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
+    b = run_gpu(dims, 3, 8, 40, 400, 170, 400, schedule="geometric", beta0=0.05, beta1=4.0, spins0=a[0],
+                layout=layout)
     assert (b[0] == full[0]).all() and (b[1] == full[1]).all()
     assert (a[3] + b[3] == full[3]).all()
 
 
-def test_replica_offset_selects_streams(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_replica_offset_selects_streams(dev, layout):
     dims = [10, 12]
-    full = run_gpu(dims, 3, 8, 24, 100)
-    part = run_gpu(dims, 3, 8, 8, 100, replica_offset=12)
-    assert (part[0] == full[0][12:20]).all()
+    full = run_gpu(dims, 3, 8, 80, 100, layout=layout)
+    part = run_gpu(dims, 3, 8, 40, 100, replica_offset=12, layout=layout)
+    assert (part[0] == full[0][12:52]).all()
 
 
-@pytest.mark.parametrize("bt", [100, 300, 512, 1000])
-def test_block_size_does_not_change_results(dev, bt):
+@pytest.mark.parametrize("bt", [1, 100, 300, 512, 1000])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_block_size_does_not_change_results(dev, bt, layout):
     c = inputs.C1
-    ref = run_gpu(c["dims"], c["weight_seed"], c["seed"], 8, 200, schedule="linear")
-    got = run_gpu(c["dims"], c["weight_seed"], c["seed"], 8, 200, schedule="linear", block_threads=bt)
-    assert (ref[0] == got[0]).all() and (ref[3] == got[3]).all()
+    ref = run_gpu(c["dims"], c["weight_seed"], c["seed"], 36, 200, schedule="linear", layout="i8")
+    got = run_gpu(c["dims"], c["weight_seed"], c["seed"], 36, 200, schedule="linear", block_threads=bt, layout=layout)
+    for x, y in zip(ref, got):
+        assert (x == y).all()
 
 
-def test_largest_on_chip_torus(dev):
-    dims = [200, 202]  # 40,400 sites: 162,816 B of LDS per block
-    gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
+@pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180])])
+def test_largest_on_chip_torus(dev, layout, dims):
+    # i8: 40,400 sites = 162,816 B of LDS per block; bp32: 32,400 sites = 162,448 B
+    gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
     orc = run_oracle(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
 
@@ -185,12 +213,19 @@ def test_too_large_torus_is_rejected(dev):
     ising = _ising()
     g = ising.create_graph([256, 256], 1)
     s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
+    for layout in ("i8", "bp32", "auto"):
+        with pytest.raises(ising.IsingError) as e:
+            ising.run_trials(g, s, 1, 10, layout=layout)
+        assert e.value.code == ising.E_UNSUPPORTED
+    g2 = ising.create_graph([200, 202], 1)
+    s2 = torch.zeros((4, g2.n), dtype=torch.int8, device="cuda")
     with pytest.raises(ising.IsingError) as e:
-        ising.run_trials(g, s, 1, 10, layout="i8")
+        ising.run_trials(g2, s2, 1, 10, layout="bp32")
     assert e.value.code == ising.E_UNSUPPORTED
 
 
-def test_invalid_input_spins_flagged(dev):
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_invalid_input_spins_flagged(dev, layout):
     import torch
 
     ising = _ising()
@@ -201,7 +236,7 @@ def test_invalid_input_spins_flagged(dev):
     s = torch.from_numpy(s0).cuda()
     cut = torch.zeros(8, dtype=torch.int64, device="cuda")
     en = torch.zeros(8, dtype=torch.int64, device="cuda")
-    ising.run_trials(g, s, 1, 10, init_spins=False, cut=cut, energy=en)
+    ising.run_trials(g, s, 1, 10, init_spins=False, cut=cut, energy=en, layout=layout)
     torch.cuda.synchronize()
     c = cut.cpu().numpy()
     assert c[3] == ising.INVALID_VALUE and c[5] == ising.INVALID_VALUE
