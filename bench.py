@@ -41,15 +41,6 @@ OPS_PER_DRAW = 40 / 4
 OPS_PER_ATTEMPT = 3
 
 
-def repetitions(p_s):
-    """eq. (3): repetitions for 99% confidence of reaching the target."""
-    if p_s <= 0.0:
-        return math.inf
-    if p_s >= 1.0:
-        return 1.0
-    return max(1.0, math.log(1 - 0.99) / math.log(1 - p_s))
-
-
 def cpu_baseline(budget_s):
     """The oracle on the host's cores: full schedules of the first replicas,
     one replica per task, until the time budget is spent.  Runs before the
@@ -119,6 +110,7 @@ def main():
     import torch
 
     import paper_2505_18508_amd as ising
+    from paper_2505_18508_amd import metrics
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -147,7 +139,7 @@ def main():
     torch.cuda.synchronize()
     blocks, draws = (int(x) for x in stats.cpu().tolist())
     best = int(cut.max().item())
-    target = math.ceil(0.999 * best)
+    target = metrics.target_cut(best)
 
     def step(ev):
         ev[0].record(stream)
@@ -155,8 +147,7 @@ def main():
         ev[1].record(stream)
         c = cut.cpu()  # readout: device -> host, then eq. (3)-(4)
         b = int(c.max())
-        p_s = float((c >= target).sum()) / R
-        return b, p_s
+        return b, metrics.success_probability(c.numpy(), target)
 
     for _ in range(args.warmup):
         step([torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)])
@@ -174,7 +165,7 @@ def main():
     ops = OPS_PER_DRAW * draws + OPS_PER_ATTEMPT * attempts
     achieved = ops / avg_kernel_s
     p_s = results[-1][1]
-    r = repetitions(p_s)
+    r = metrics.repetitions(p_s)
 
     out = {
         "metric": "spin-update attempts/s on 1 MI355X",
