@@ -41,6 +41,23 @@ OPS_PER_DRAW = 40 / 4
 OPS_PER_ATTEMPT = 3
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter profile, or None when
+    there is none or the kernel source changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("%s/%s" % (kernel, workload))
+    if rec is None:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
 def cpu_baseline(budget_s):
     """The oracle on the host's cores: full schedules of the first replicas,
     one replica per task, until the time budget is spent.  Runs before the
@@ -95,6 +112,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB device-to-device (a reference kernel of known traffic for counters)")
     args = ap.parse_args()
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]
@@ -115,6 +134,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     W = WORKLOAD
     g = ising.create_graph(W["dims"], W["weight_seed"])
     R, S, n = W["R"], W["S"], g.n
@@ -184,7 +209,8 @@ def main():
         "kernel_attempts_per_s": attempts / avg_kernel_s,
         "kernel_ms": avg_kernel_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_LANE_OPS, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_LANE_OPS,
+                     "traffic": measured_traffic(kernel_name, args.workload),
                      "kernel": kernel_name, "philox_blocks": blocks, "draws": draws,
                      "draw_fraction": draws / attempts},
         "readout": {"best_cut": results[-1][0], "target": target, "P_s": p_s, "r": r, "STT_sweeps": S * r},

@@ -176,6 +176,106 @@ int ising_thresholds(const ising_run_params* p, int32_t degree, uint32_t* host_o
  * Asynchronous on `stream`. */
 int ising_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned culling.  A small network reads per-replica trajectory features
+ * at sweep checkpoints and predicts each replica's end-of-trial cut, so
+ * that unpromising replicas are replaced by copies of promising ones.  (The
+ * paper's trials are independent runs read out at their end, Section III;
+ * culling is this library's extension of that campaign, and the plain
+ * all-trials run remains the reference it is judged against with eq. (3).)
+ * ---------------------------------------------------------------------- */
+
+#define ISING_N_FEATURES 16
+#define ISING_MLP_HIDDEN 64
+/* parameters, in order: W1 [64][16], b1 [64], W2 [64][64], b2 [64], W3 [64], b3 [1] */
+#define ISING_MLP_PARAMS 5313
+
+/* Per-replica trajectory record kept across checkpoints (device memory,
+ * caller-owned, zero-filled before the first checkpoint of a trial). */
+typedef struct {
+  int64_t h_min;           /* lowest checkpoint energy so far                   */
+  int64_t h_prev;          /* energy at the previous checkpoint                 */
+  uint64_t flips_total;    /* accepted flips since the start of the trial       */
+  int32_t checkpoints;     /* checkpoints recorded so far                       */
+  int32_t last_improve;    /* checkpoint index at which h_min last decreased    */
+} ising_track;
+
+/*
+ * Features of R replicas at a checkpoint after `sweeps_done` sweeps of an
+ * S-sweep schedule, the last window having `window` sweeps.
+ *   spins        device int8 [R][n], canonical layout (state at the checkpoint).
+ *   energy       device int64 [R]: eq. (2) energy of that state (run output).
+ *   window_flips device uint32 [R]: accepted flips of the last window.
+ *   track        device ising_track [R], updated in place.
+ *   beta         inverse temperature of the window's last sweep (> 0).
+ *   n_checkpoints total checkpoints of the trial (>= 1).
+ *   features     device float [R][16]:
+ *     0 H/|E|, 1 min over checkpoints of H/|E|, 2 (H - H_prev)/|E| (H_prev = 0
+ *     at the first checkpoint), 3 window flips/(n window), 4 total flips/(n
+ *     sweeps_done), 5 beta, 6 sweeps_done/S, 7..13 fraction of sites with
+ *     s_i f_i = -6, -4, -2, 0, 2, 4, 6 (f_i = sum_j w_ij s_j), 14 ln beta,
+ *     15 (checkpoints since h_min last decreased) / n_checkpoints.
+ * Asynchronous on `stream`.
+ */
+int ising_features(const ising_graph* g, const int8_t* spins, const int64_t* energy,
+                   const uint32_t* window_flips, int64_t n_replicas, ising_track* track,
+                   int32_t sweeps_done, int32_t window, int32_t n_sweeps, double beta,
+                   int32_t n_checkpoints, float* features, void* stream);
+
+/* Kaiming-uniform initial parameters from Philox (key = seed, counter
+ * (index >> 2, 0, 0, 3), word index & 3): a weight of a layer with fan-in F
+ * is sqrt(6/F) * (2 u - 1), u = (word >> 8) * 2^-24; biases 0.
+ * params: device float [ISING_MLP_PARAMS].  Asynchronous. */
+int ising_mlp_init(uint64_t seed, float* params, void* stream);
+
+/* y[b] = W3 relu(W2 relu(W1 z_b + b1) + b2) + b3 with z_b = (x_b - mean) / std
+ * (mean, std: device float[16], or both NULL for z = x).
+ * x device float [B][16] (rows idx[b] when idx != NULL: device int32 [B]);
+ * y device float [B].  Asynchronous. */
+int ising_mlp_forward(const float* params, const float* x, const int32_t* idx, const float* mean,
+                      const float* std, int64_t batch, float* y, void* stream);
+
+/* Floats of workspace ising_mlp_loss_grad needs for a batch. */
+int64_t ising_mlp_workspace_floats(int64_t batch);
+
+/* Mean squared error L = (1/B) sum_b (y_b - target_b)^2 of the forward pass
+ * above and its gradient with respect to every parameter.
+ *   target    device float [B] (entries idx[b] when idx != NULL).
+ *   grad      device float [ISING_MLP_PARAMS] (overwritten).
+ *   loss      device float [1] (overwritten), or NULL.
+ *   workspace device float [ising_mlp_workspace_floats(B)].
+ * Summation order is fixed, so results are reproducible.  Asynchronous. */
+int ising_mlp_loss_grad(const float* params, const float* x, const int32_t* idx, const float* mean,
+                        const float* std, const float* target, int64_t batch, float* grad,
+                        float* loss, float* workspace, void* stream);
+
+/* One Adam step (Kingma & Ba) on n parameters, step = 1, 2, ...:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  Asynchronous. */
+int ising_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                    float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Column means and standard deviations (population, floored at 1e-6) of a
+ * device float [rows][16] table, computed in double with a fixed summation
+ * order; mean, std: device float [16].  Asynchronous. */
+int ising_feature_stats(const float* x, int64_t rows, float* mean, float* std, void* stream);
+
+/*
+ * Rank R replicas by score (higher first; ties: lower index first; NaN
+ * last) and let the bottom floor(R/2) take copies of the top floor(R/2):
+ * the j-th worst becomes a copy of the j-th best (spins and, when track is
+ * not NULL, its ising_track).  Each replica keeps its index, hence its own
+ * Philox stream, so copies diverge afterwards.
+ *   score     device float [R];  spins device int8 [R][n] (in/out).
+ *   order_out device int32 [R] or NULL: replica indices from best to worst.
+ * R <= 16384.  Asynchronous.
+ */
+int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, int8_t* spins,
+                     ising_track* track, int32_t* order_out, void* stream);
+
+/* score[r] = -energy[r] (the energy-ranked baseline of culling). */
+int ising_energy_score(const int64_t* energy, int64_t n_replicas, float* score, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* ising_last_error(void);
 

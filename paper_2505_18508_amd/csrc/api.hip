@@ -17,23 +17,10 @@
 
 using ising::Lattice;
 
+using ising::fail;
+using ising::fail_hip;
+
 namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return code;
-}
-
-int fail_hip(hipError_t e, const char* what) {
-  return fail(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e));
-}
 
 struct DeviceInfo {
   int cus = 0;
@@ -227,9 +214,27 @@ int check_device(const ising_graph* g) {
 
 }  // namespace
 
+namespace ising {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) { return fail(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e)); }
+
+}  // namespace ising
+
 extern "C" {
 
-const char* ising_last_error(void) { return g_last_error.c_str(); }
+const char* ising_last_error(void) { return ising::g_last_error.c_str(); }
 
 int ising_generate_weights(int32_t ndim, const int32_t* dims, uint64_t weight_seed, int8_t* host_out) {
   int rc = check_dims(ndim, dims);

@@ -33,6 +33,10 @@ struct ising_graph {
 
 namespace ising {
 
+// Record a message for ising_last_error() and return code.
+int fail(int code, const char* fmt, ...);
+int fail_hip(hipError_t e, const char* what);
+
 // Work description of one sweep-kernel launch (device pointers).
 struct SweepLaunch {
   const uint32_t* d_thr;  // full-schedule threshold table [S][kmax]
