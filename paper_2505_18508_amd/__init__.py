@@ -29,7 +29,11 @@ EXPORTED = [
     "ising_create_graph", "ising_destroy_graph", "ising_graph_info", "ising_graph_weights",
     "ising_generate_weights", "ising_run_trials", "ising_eval_cut", "ising_thresholds",
     "ising_philox_dump", "ising_last_error",
+    "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
+    "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score",
 ]
+N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
+TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
 
 
 class IsingError(RuntimeError):
@@ -81,9 +85,20 @@ def lib():
         L.ising_philox_dump.argtypes = [u64, vp, i64, vp, vp]
         L.ising_last_error.argtypes = []
         L.ising_last_error.restype = ctypes.c_char_p
+        f32 = ctypes.c_float
+        L.ising_features.argtypes = [vp, vp, vp, vp, i64, vp, i32, i32, i32, ctypes.c_double, i32, vp, vp]
+        L.ising_mlp_init.argtypes = [u64, vp, vp]
+        L.ising_mlp_forward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.ising_mlp_workspace_floats.argtypes = [i64]
+        L.ising_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.ising_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
+        L.ising_feature_stats.argtypes = [vp, i64, vp, vp, vp]
+        L.ising_cull_clone.argtypes = [vp, i64, i64, vp, vp, vp, vp]
+        L.ising_energy_score.argtypes = [vp, i64, vp, vp]
         for name in EXPORTED:
-            if name != "ising_destroy_graph" and name != "ising_last_error":
+            if name not in ("ising_destroy_graph", "ising_last_error", "ising_mlp_workspace_floats"):
                 getattr(L, name).restype = ctypes.c_int
+        L.ising_mlp_workspace_floats.restype = i64
         _lib = L
     return _lib
 
@@ -226,3 +241,62 @@ def thresholds(n_sweeps, schedule="linear", beta0=0.1, beta1=3.0, beta_table=Non
 def philox_dump(key, ctr, out, stream=None):
     """Philox4x32-10 blocks on the GPU: ctr, out uint32/int32 device [m][4]."""
     _check(lib().ising_philox_dump(int(key), _ptr(ctr), ctr.shape[0], _ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Learned culling
+# ---------------------------------------------------------------------------
+def new_track(n_replicas, device=None):
+    """Zeroed per-replica trajectory records (ising_track [R])."""
+    import torch
+
+    return torch.zeros((n_replicas, TRACK_WORDS), dtype=torch.int64, device=device or "cuda")
+
+
+def features(graph, spins, energy, window_flips, track, sweeps_done, window, n_sweeps, beta, n_checkpoints, out,
+             stream=None):
+    """ising_features: out float32 [R][16]; track updated in place."""
+    R = spins.shape[0]
+    _check(lib().ising_features(graph.handle, _ptr(spins), _ptr(energy), _ptr(window_flips), R, _ptr(track),
+                                int(sweeps_done), int(window), int(n_sweeps), float(beta), int(n_checkpoints),
+                                _ptr(out), _stream(stream)))
+
+
+def mlp_init(seed, params, stream=None):
+    _check(lib().ising_mlp_init(int(seed), _ptr(params), _stream(stream)))
+
+
+def mlp_forward(params, x, y, idx=None, mean=None, std=None, batch=None, stream=None):
+    B = (idx.shape[0] if idx is not None else x.shape[0]) if batch is None else int(batch)
+    _check(lib().ising_mlp_forward(_ptr(params), _ptr(x), _ptr(idx), _ptr(mean), _ptr(std), B, _ptr(y),
+                                   _stream(stream)))
+
+
+def mlp_workspace_floats(batch):
+    return int(lib().ising_mlp_workspace_floats(int(batch)))
+
+
+def mlp_loss_grad(params, x, target, grad, workspace, loss=None, idx=None, mean=None, std=None, batch=None,
+                  stream=None):
+    B = (idx.shape[0] if idx is not None else x.shape[0]) if batch is None else int(batch)
+    _check(lib().ising_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(idx), _ptr(mean), _ptr(std), _ptr(target), B,
+                                     _ptr(grad), _ptr(loss), _ptr(workspace), _stream(stream)))
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().ising_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step), float(lr),
+                                 float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def feature_stats(x, mean, std, rows=None, stream=None):
+    n = x.shape[0] if rows is None else int(rows)
+    _check(lib().ising_feature_stats(_ptr(x), n, _ptr(mean), _ptr(std), _stream(stream)))
+
+
+def cull_clone(score, spins, track=None, order=None, stream=None):
+    R, n = spins.shape
+    _check(lib().ising_cull_clone(_ptr(score), R, n, _ptr(spins), _ptr(track), _ptr(order), _stream(stream)))
+
+
+def energy_score(energy, score, stream=None):
+    _check(lib().ising_energy_score(_ptr(energy), energy.shape[0], _ptr(score), _stream(stream)))
