@@ -171,6 +171,9 @@ int ising_eval_cut(const ising_graph* g, const int8_t* spins, int64_t n_replicas
  * S-sweep schedule of p, into host uint32 [S][degree/2].  degree is 4 or 6. */
 int ising_thresholds(const ising_run_params* p, int32_t degree, uint32_t* host_out);
 
+/* Host-only: inverse temperature beta_t of sweep t of p's schedule (0 <= t < S). */
+int ising_schedule_beta(const ising_run_params* p, int32_t t, double* beta_out);
+
 /* Philox4x32-10 blocks on the GPU (the generator the kernels use), for
  * cross-checks: device uint32 ctr[m][4] in, device uint32 out[m][4] out.
  * Asynchronous on `stream`. */

@@ -30,7 +30,7 @@ EXPORTED = [
     "ising_generate_weights", "ising_run_trials", "ising_eval_cut", "ising_thresholds",
     "ising_philox_dump", "ising_last_error",
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
-    "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score",
+    "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -95,6 +95,7 @@ def lib():
         L.ising_feature_stats.argtypes = [vp, i64, vp, vp, vp]
         L.ising_cull_clone.argtypes = [vp, i64, i64, vp, vp, vp, vp]
         L.ising_energy_score.argtypes = [vp, i64, vp, vp]
+        L.ising_schedule_beta.argtypes = [ctypes.POINTER(RunParams), i32, ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTED:
             if name not in ("ising_destroy_graph", "ising_last_error", "ising_mlp_workspace_floats"):
                 getattr(L, name).restype = ctypes.c_int
@@ -236,6 +237,15 @@ def thresholds(n_sweeps, schedule="linear", beta0=0.1, beta1=3.0, beta_table=Non
     _check(lib().ising_thresholds(ctypes.byref(p), int(degree), out.ctypes.data))
     del keep
     return out
+
+
+def schedule_beta(n_sweeps, t, schedule="linear", beta0=0.1, beta1=3.0, beta_table=None):
+    """beta_t of sweep t of an n_sweeps schedule (the library's own schedule)."""
+    p, keep = make_params(0, 1, n_sweeps, 0, None, schedule, beta0, beta1, beta_table)
+    out = ctypes.c_double()
+    _check(lib().ising_schedule_beta(ctypes.byref(p), int(t), ctypes.byref(out)))
+    del keep
+    return out.value
 
 
 def philox_dump(key, ctr, out, stream=None):

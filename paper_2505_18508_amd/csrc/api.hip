@@ -339,6 +339,15 @@ int ising_thresholds(const ising_run_params* p, int32_t degree, uint32_t* host_o
   return ISING_OK;
 }
 
+int ising_schedule_beta(const ising_run_params* p, int32_t t, double* beta_out) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (t < 0 || t >= p->n_sweeps) return fail(ISING_E_ARG, "sweep %d outside [0, %d)", t, p->n_sweeps);
+  if (!beta_out) return fail(ISING_E_ARG, "beta_out is NULL");
+  *beta_out = schedule_beta(p, t);
+  return ISING_OK;
+}
+
 int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout, int64_t* cut_out,
                      int64_t* energy_out, uint32_t* flips_out, void* stream) {
   if (!g) return fail(ISING_E_ARG, "graph is NULL");
