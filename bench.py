@@ -30,6 +30,13 @@ WORKLOADS = {
                name="2-D torus 100x200 (20,000 spins, weight seed 81), 8,192 replicas, 40,000 sweeps, "
                     "geometric beta 0.05->4.0, run seed 201"),
 }
+WORKLOADS["c3"] = dict(
+    instances=[([50, 100], 11, 111, 256, 5000), ([100, 100], 12, 112, 1024, 10000), ([100, 140], 13, 113, 2048, 15000),
+               ([100, 200], 14, 114, 4096, 20000)],
+    schedule="geometric", beta0=0.05, beta1=4.0,
+    name="batch of 2-D tori 50x100 / 100x100 / 100x140 / 100x200 (weight seeds 11-14) with 256 / 1,024 / 2,048 / "
+         "4,096 replicas and 5,000 / 10,000 / 15,000 / 20,000 sweeps in one persistent launch, geometric beta "
+         "0.05->4.0, run seeds 111-114")
 WORKLOAD = WORKLOADS["c2"]
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU issue
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
@@ -102,6 +109,65 @@ def _oracle_one(r, w, wl):
     return r, s[0]
 
 
+def bench_batch(args, ising, metrics, torch, dev):
+    """The uneven-instance batch: one step = one persistent launch over all
+    instances, plus the readout of every instance's cuts."""
+    W = WORKLOAD
+    graphs, runs = [], []
+    for dims, wseed, seed, R, S in W["instances"]:
+        g = ising.create_graph(dims, wseed)
+        graphs.append(g)
+        runs.append(dict(seed=seed, n_sweeps=S, schedule=W["schedule"], beta0=W["beta0"], beta1=W["beta1"],
+                         spins=torch.zeros((R, g.n), dtype=torch.int8, device=dev),
+                         cut=torch.zeros(R, dtype=torch.int64, device=dev)))
+    batch = ising.Batch(graphs, runs)
+    stream = torch.cuda.current_stream()
+    # algorithmic work: RNG draws of the same trajectories, from instrumented single runs (untimed)
+    draws = 0
+    for g, run in zip(graphs, runs):
+        st = torch.zeros(2, dtype=torch.int64, device=dev)
+        tmp = torch.zeros_like(run["spins"])
+        ising.run_trials(g, tmp, run["seed"], run["n_sweeps"], schedule=run["schedule"], beta0=run["beta0"],
+                         beta1=run["beta1"], layout="i8", stats=st)
+        torch.cuda.synchronize()
+        draws += int(st[1].item())
+        del tmp
+
+    def step(ev):
+        ev[0].record(stream)
+        batch.run(stream)
+        ev[1].record(stream)
+        return [int(r["cut"].max().item()) for r in runs]
+
+    for _ in range(args.warmup):
+        step([torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)])
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    bests = [step(ev) for ev in events][-1]
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    kernel_s = sum(e[0].elapsed_time(e[1]) for e in events) / len(events) / 1e3
+    attempts = batch.attempts
+    ops = OPS_PER_DRAW * draws + OPS_PER_ATTEMPT * attempts
+    out = {
+        "metric": "spin-update attempts/s on 1 MI355X", "value": attempts * args.steps / total_s,
+        "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total_s * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": W["name"], "layout": "i8", "work_items": batch.n_items, "grid": batch.grid,
+                   "block": batch.block},
+        "kernel_attempts_per_s": attempts / kernel_s, "kernel_ms": kernel_s * 1e3,
+        "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                     "unit": "Tlane-op/s", "frac": ops / kernel_s / VALU_PEAK_LANE_OPS,
+                     "traffic": measured_traffic("k_sweep_i8_batch", "c3"), "kernel": "k_sweep_i8_batch",
+                     "draws": draws, "draw_fraction": draws / attempts},
+        "readout": {"best_cut_per_instance": bests},
+    }
+    batch.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +183,8 @@ def main():
     args = ap.parse_args()
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]
+    if args.workload == "c3":
+        args.no_cpu = True  # the oracle baseline is measured on the single-instance workloads
     if args.gpus != 1:
         print("bench.py measures one GPU only: the replica-parallel path has no cross-GPU step to time "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -141,6 +209,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     W = WORKLOAD
+    if args.workload == "c3":
+        print(json.dumps(bench_batch(args, ising, metrics, torch, dev)))
+        return
     g = ising.create_graph(W["dims"], W["weight_seed"])
     R, S, n = W["R"], W["S"], g.n
     spins = torch.zeros((R, n), dtype=torch.int8, device=dev)

@@ -180,6 +180,41 @@ int ising_schedule_beta(const ising_run_params* p, int32_t t, double* beta_out);
 int ising_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batches of uneven instances in one persistent launch.  Every (instance,
+ * replica quad) pair is a work item; items are taken costliest first
+ * (sites x sweeps) from a device queue by resident blocks until it is empty.
+ * Each replica's trajectory is identical to the one ising_run_trials gives
+ * for the same instance and parameters.
+ * ---------------------------------------------------------------------- */
+typedef struct ising_batch ising_batch;
+
+/*
+ * Prepare a batch (synchronous; allocates the plan's device tables).
+ *   n_inst               >= 1 instances, all with the same ndim.
+ *   graphs[k], params[k] instance k and its run (layout AUTO or I8;
+ *                        stats_out must be NULL).
+ *   spins[k]             device int8 [R_k][n_k] (in/out, as ising_run_trials).
+ *   cut_out, energy_out, flips_out  NULL, or arrays of n_inst device
+ *                        pointers (entries may be NULL).
+ * The graphs and buffers must outlive the batch.
+ */
+int ising_batch_create(int32_t n_inst, const ising_graph* const* graphs, const ising_run_params* params,
+                       int8_t* const* spins, int64_t* const* cut_out, int64_t* const* energy_out,
+                       uint32_t* const* flips_out, ising_batch** out);
+
+/* Enqueue the whole batch on `stream`: a counter reset and one persistent
+ * launch, with no allocation and no memset, so the call can be captured
+ * into a HIP graph and replayed.  Runs on one stream at a time (the queue
+ * counter is the plan's). */
+int ising_batch_run(ising_batch* b, void* stream);
+
+/* Work items, total spin-update attempts, grid and block of the launch. */
+int ising_batch_info(const ising_batch* b, int64_t* n_items, int64_t* attempts, int32_t* grid, int32_t* block);
+
+/* Free a batch plan (NULL-safe).  Work that uses it must have completed. */
+void ising_batch_destroy(ising_batch* b);
+
+/* ------------------------------------------------------------------------
  * Learned culling.  A small network reads per-replica trajectory features
  * at sweep checkpoints and predicts each replica's end-of-trial cut, so
  * that unpromising replicas are replaced by copies of promising ones.  (The

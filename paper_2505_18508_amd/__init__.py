@@ -31,6 +31,7 @@ EXPORTED = [
     "ising_philox_dump", "ising_last_error",
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
+    "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -96,8 +97,14 @@ def lib():
         L.ising_cull_clone.argtypes = [vp, i64, i64, vp, vp, vp, vp]
         L.ising_energy_score.argtypes = [vp, i64, vp, vp]
         L.ising_schedule_beta.argtypes = [ctypes.POINTER(RunParams), i32, ctypes.POINTER(ctypes.c_double)]
+        L.ising_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+        L.ising_batch_run.argtypes = [vp, vp]
+        L.ising_batch_info.argtypes = [vp, vp, vp, vp, vp]
+        L.ising_batch_destroy.argtypes = [vp]
+        L.ising_batch_destroy.restype = None
         for name in EXPORTED:
-            if name not in ("ising_destroy_graph", "ising_last_error", "ising_mlp_workspace_floats"):
+            if name not in ("ising_destroy_graph", "ising_last_error", "ising_mlp_workspace_floats",
+                            "ising_batch_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         L.ising_mlp_workspace_floats.restype = i64
         _lib = L
@@ -310,3 +317,56 @@ def cull_clone(score, spins, track=None, order=None, stream=None):
 
 def energy_score(energy, score, stream=None):
     _check(lib().ising_energy_score(_ptr(energy), energy.shape[0], _ptr(score), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Batches of uneven instances
+# ---------------------------------------------------------------------------
+class Batch:
+    """A prepared persistent launch over several (graph, run) pairs.  Each run
+    is a dict of run_trials keyword arguments plus `spins` (device int8
+    [R][n]) and optional `cut`, `energy`, `flips` device tensors."""
+
+    def __init__(self, graphs, runs):
+        k = len(graphs)
+        if k != len(runs) or k == 0:
+            raise ValueError("need one run per graph")
+        self._keep = []
+        params = (RunParams * k)()
+        ptrs = {name: (ctypes.c_void_p * k)() for name in ("spins", "cut", "energy", "flips")}
+        gh = (ctypes.c_void_p * k)(*[g.handle.value for g in graphs])
+        for i, (g, run) in enumerate(zip(graphs, runs)):
+            spins = run["spins"]
+            if spins.dim() != 2 or spins.shape[1] != g.n:
+                raise ValueError("spins of instance %d must be [R][%d]" % (i, g.n))
+            p, keep = make_params(run["seed"], spins.shape[0], run["n_sweeps"], run.get("sweep_begin", 0),
+                                  run.get("sweep_end"), run.get("schedule", "geometric"), run.get("beta0", 0.05),
+                                  run.get("beta1", 4.0), run.get("beta_table"), run.get("init_spins", True),
+                                  run.get("layout", "auto"), 0, run.get("replica_offset", 0))
+            params[i] = p
+            self._keep.append(keep)
+            for name in ptrs:
+                t = run.get(name)
+                ptrs[name][i] = None if t is None else _ptr(t).value
+        h = ctypes.c_void_p()
+        _check(lib().ising_batch_create(k, gh, params, ptrs["spins"], ptrs["cut"], ptrs["energy"], ptrs["flips"],
+                                        ctypes.byref(h)))
+        self._h = h
+        self.graphs, self.runs = graphs, runs
+        n, a, gr, bl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ising_batch_info(h, ctypes.byref(n), ctypes.byref(a), ctypes.byref(gr), ctypes.byref(bl)))
+        self.n_items, self.attempts, self.grid, self.block = n.value, a.value, gr.value, bl.value
+
+    def run(self, stream=None):
+        _check(lib().ising_batch_run(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ising_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -156,7 +156,7 @@ constexpr size_t kMaxCachedTables = 64;
 // tables are immutable and freed with the graph; beyond the cache size a
 // stream-ordered allocation is made and released after the launch.
 int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t stream, uint32_t** out,
-                    bool* owned) {
+                    bool* owned, bool for_plan = false) {
   const int kmax = g->degree / 2;
   const uint64_t th = p->schedule == ISING_SCHED_TABLE ? fnv1a(p->beta_table, sizeof(double) * p->n_sweeps) : 0;
   const double b0 = p->schedule == ISING_SCHED_TABLE ? 0.0 : p->beta0;
@@ -190,6 +190,18 @@ int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t
     return ISING_OK;
   }
   uint32_t* d = nullptr;
+  if (for_plan) {  // kept by a batch plan and freed with it
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(ISING_E_NOMEM, "threshold table (%zu bytes): %s", bytes, hipGetErrorString(e));
+    e = hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return fail_hip(e, "threshold table upload");
+    }
+    *out = d;
+    *owned = true;
+    return ISING_OK;
+  }
   hipError_t e = hipMallocAsync((void**)&d, bytes, stream);
   if (e != hipSuccess) return fail(ISING_E_NOMEM, "threshold table (%zu bytes): %s", bytes, hipGetErrorString(e));
   e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, stream);
@@ -348,8 +360,12 @@ int ising_schedule_beta(const ising_run_params* p, int32_t t, double* beta_out) 
   return ISING_OK;
 }
 
-int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout, int64_t* cut_out,
-                     int64_t* energy_out, uint32_t* flips_out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Validation shared by single runs and batches; picks the layout.
+int check_run(const ising_graph* g, const ising_run_params* p, const int8_t* spins_inout, int* layout_out) {
   if (!g) return fail(ISING_E_ARG, "graph is NULL");
   int rc = check_params(p);
   if (rc) return rc;
@@ -360,11 +376,10 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
   if (!spins_inout) return fail(ISING_E_ARG, "spins_inout is NULL");
   if (p->replica_offset < 0 || (int64_t)p->replica_offset + p->n_replicas > INT32_MAX)
     return fail(ISING_E_ARG, "replica_offset out of range");
+  if (p->replica_offset % 4 != 0) return fail(ISING_E_ARG, "replica_offset must be a multiple of 4");
   rc = check_device(g);
   if (rc) return rc;
   const DeviceInfo dev = device_info(g->device);
-
-  if (p->replica_offset % 4 != 0) return fail(ISING_E_ARG, "replica_offset must be a multiple of 4");
   const bool i8_fits = ising::sweep_i8_block(g->lat, p->block_threads) > 0 &&
                        ising::sweep_i8_lds_bytes(g->lat) <= dev.lds_per_block;
   const bool bp_fits = ising::sweep_bp32_block(g->lat, p->block_threads) > 0 &&
@@ -376,23 +391,22 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
     const int64_t groups = ((int64_t)p->n_replicas + 31) / 32;
     layout = (bp_fits && (groups >= dev.cus || !i8_fits)) ? ISING_LAYOUT_BP32 : ISING_LAYOUT_I8;
   }
-  if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32)
-    return fail(ISING_E_ARG, "unknown layout %d", p->layout);
+  if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32) return fail(ISING_E_ARG, "unknown layout %d", p->layout);
   if ((layout == ISING_LAYOUT_I8 && !i8_fits) || (layout == ISING_LAYOUT_BP32 && !bp_fits))
     return fail(ISING_E_UNSUPPORTED, "torus of %lld sites does not fit the on-chip sweep kernel of layout %d",
                 (long long)g->n, layout);
+  *layout_out = layout;
+  return ISING_OK;
+}
 
-  hipStream_t st = (hipStream_t)stream;
-  uint32_t* d_thr = nullptr;
-  bool owned = false;
-  rc = threshold_table(g, p, st, &d_thr, &owned);
-  if (rc) return rc;
+ising::SweepLaunch make_launch(const ising_run_params* p, const uint32_t* d_thr, int8_t* spins, int64_t* cut,
+                               int64_t* energy, uint32_t* flips) {
   ising::SweepLaunch s;
   s.d_thr = d_thr;
-  s.spins = spins_inout;
-  s.cut = cut_out;
-  s.energy = energy_out;
-  s.flips = flips_out;
+  s.spins = spins;
+  s.cut = cut;
+  s.energy = energy;
+  s.flips = flips;
   s.stats = (unsigned long long*)p->stats_out;
   s.seed = p->seed;
   s.n_replicas = p->n_replicas;
@@ -401,10 +415,106 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
   s.t_end = p->sweep_end;
   s.init = p->init_spins ? 1 : 0;
   s.block_threads = p->block_threads;
+  return s;
+}
+
+}  // namespace
+
+struct ising_batch {
+  ising::I8BatchPlan plan;
+  std::vector<uint32_t*> owned_tables;
+  int64_t attempts = 0;
+  int device = 0;
+};
+
+extern "C" {
+
+int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout, int64_t* cut_out,
+                     int64_t* energy_out, uint32_t* flips_out, void* stream) {
+  int layout = 0;
+  int rc = check_run(g, p, spins_inout, &layout);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* d_thr = nullptr;
+  bool owned = false;
+  rc = threshold_table(g, p, st, &d_thr, &owned);
+  if (rc) return rc;
+  const ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
   hipError_t e = layout == ISING_LAYOUT_BP32 ? ising::launch_sweep_bp32(g, s, st) : ising::launch_sweep_i8(g, s, st);
   if (owned) (void)hipFreeAsync(d_thr, st);
   if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");
   return ISING_OK;
+}
+
+int ising_batch_create(int32_t n_inst, const ising_graph* const* graphs, const ising_run_params* params,
+                       int8_t* const* spins, int64_t* const* cut_out, int64_t* const* energy_out,
+                       uint32_t* const* flips_out, ising_batch** out) {
+  if (!out) return fail(ISING_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_inst < 1 || !graphs || !params || !spins) return fail(ISING_E_ARG, "need n_inst >= 1 and graphs, params, spins");
+  ising_batch* b = new (std::nothrow) ising_batch();
+  if (!b) return fail(ISING_E_NOMEM, "batch handle");
+  std::vector<ising::SweepLaunch> launches((size_t)n_inst);
+  auto bail = [&](int code) {
+    for (uint32_t* t : b->owned_tables) (void)hipFree(t);
+    delete b;
+    return code;
+  };
+  for (int k = 0; k < n_inst; ++k) {
+    const ising_graph* g = graphs[k];
+    const ising_run_params* p = &params[k];
+    int layout = 0;
+    int rc = check_run(g, p, spins[k], &layout);
+    if (rc) return bail(rc);
+    if (g->ndim != graphs[0]->ndim) return bail(fail(ISING_E_ARG, "instances of a batch must share ndim"));
+    if (p->layout != ISING_LAYOUT_AUTO && p->layout != ISING_LAYOUT_I8)
+      return bail(fail(ISING_E_UNSUPPORTED, "batches use the four-replica layout"));
+    if (ising::sweep_i8_lds_bytes(g->lat) > device_info(g->device).lds_per_block || ising::sweep_i8_block(g->lat, 0) <= 0)
+      return bail(fail(ISING_E_UNSUPPORTED, "instance %d does not fit the four-replica kernel", k));
+    if (p->stats_out) return bail(fail(ISING_E_UNSUPPORTED, "batches do not collect RNG statistics"));
+    uint32_t* d_thr = nullptr;
+    bool owned = false;
+    rc = threshold_table(g, p, nullptr, &d_thr, &owned, true);
+    if (rc) return bail(rc);
+    if (owned) b->owned_tables.push_back(d_thr);  // kept for the plan's lifetime
+    launches[(size_t)k] = make_launch(p, d_thr, spins[k], cut_out ? cut_out[k] : nullptr,
+                                      energy_out ? energy_out[k] : nullptr, flips_out ? flips_out[k] : nullptr);
+    b->attempts += (int64_t)p->n_replicas * g->n * (p->sweep_end - p->sweep_begin);
+  }
+  b->device = graphs[0]->device;
+  hipError_t e = ising::build_i8_batch(graphs, launches.data(), n_inst, &b->plan);
+  if (e != hipSuccess) {
+    ising::free_i8_batch(b->plan);
+    return bail(fail_hip(e, "batch plan"));
+  }
+  *out = b;
+  return ISING_OK;
+}
+
+int ising_batch_run(ising_batch* b, void* stream) {
+  if (!b) return fail(ISING_E_ARG, "batch is NULL");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (dev != b->device) return fail(ISING_E_STATE, "batch lives on device %d but device %d is current", b->device, dev);
+  e = ising::run_i8_batch(b->plan, (hipStream_t)stream);
+  return e == hipSuccess ? ISING_OK : fail_hip(e, "batch launch");
+}
+
+int ising_batch_info(const ising_batch* b, int64_t* n_items, int64_t* attempts, int32_t* grid, int32_t* block) {
+  if (!b) return fail(ISING_E_ARG, "batch is NULL");
+  if (n_items) *n_items = b->plan.n_items;
+  if (attempts) *attempts = b->attempts;
+  if (grid) *grid = b->plan.grid;
+  if (block) *block = b->plan.block;
+  return ISING_OK;
+}
+
+void ising_batch_destroy(ising_batch* b) {
+  if (!b) return;
+  ising::free_i8_batch(b->plan);
+  for (uint32_t* t : b->owned_tables) (void)hipFree(t);
+  delete b;
 }
 
 int ising_eval_cut(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut_out,

@@ -23,6 +23,10 @@
 // with cut = (W_total - H) / 2 (eq. (1)).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <utility>
+#include <vector>
+
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -32,6 +36,11 @@ namespace {
 constexpr int kMaxBlock = 1024;
 constexpr int kExtraWords = 16;  // [0,4) flips, 4 invalid flags, [8,12) energy sums
 constexpr int kLut = 144;        // threshold table entries: (spin bit << 7) | field, field <= 12
+
+struct BatchItem {
+  int32_t inst;  // instance
+  int32_t r0;    // first local replica of the quad
+};
 
 struct I8Args {
   Lattice lat;
@@ -94,9 +103,10 @@ __device__ __forceinline__ uint32_t thr_for_g(uint32_t g, uint32_t t1, uint32_t 
   return g == 0u ? t3 : (g == 2u ? t2 : t1);
 }
 
+// One replica quad (local replicas r0 .. r0+3) for the window of a.  Called
+// by every thread of a block; lds holds sweep_i8_lds_bytes(a.lat) bytes.
 template <int NDIM, bool STATS>
-__global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
-  extern __shared__ uint32_t lds[];
+__device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t* lds) {
   constexpr int DEG = 2 * NDIM;
   constexpr uint32_t kOnes = 0x01010101u;
   const Lattice& L = a.lat;
@@ -104,7 +114,6 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
   const int B = blockDim.x;
   uint32_t* extra = lds + L.n;
 
-  const int r0 = blockIdx.x * 4;                     // first local replica of this quad
   const int nvalid = min(4, a.n_replicas - r0);
   const uint32_t quad = (uint32_t)(a.replica_offset + r0) >> 2;
   const size_t n = (size_t)L.n;
@@ -343,6 +352,34 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
   }
 }
 
+template <int NDIM, bool STATS>
+__global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
+  extern __shared__ uint32_t lds[];
+  i8_quad<NDIM, STATS>(a, blockIdx.x * 4, lds);
+}
+
+// Persistent launch over a queue of (instance, quad) items, costliest
+// first: each block takes the next item from a global counter until the
+// queue is empty, so every block reaches the exit.
+template <int NDIM>
+__global__ void __launch_bounds__(kMaxBlock) k_sweep_i8_batch(const I8Args* inst, const BatchItem* items, int n_items,
+                                                              unsigned int* counter) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = next;
+    __syncthreads();
+    if (it >= n_items) break;
+    const BatchItem bi = items[it];
+    i8_quad<NDIM, false>(inst[bi.inst], bi.r0, lds);
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_counter(unsigned int* counter) { *counter = 0u; }
+
 }  // namespace
 
 size_t sweep_i8_lds_bytes(const Lattice& L) { return ((size_t)L.n + kExtraWords + 2 * kLut) * 4u; }
@@ -401,6 +438,88 @@ hipError_t launch_sweep_i8(const ising_graph* g, const SweepLaunch& s, hipStream
     e = s.stats ? go(k_sweep_i8<3, true>) : go(k_sweep_i8<3, false>);
   if (e != hipSuccess) return e;
   return hipGetLastError();
+}
+
+}  // namespace ising
+
+namespace ising {
+
+hipError_t build_i8_batch(const ising_graph* const* graphs, const SweepLaunch* launches, int n_inst, I8BatchPlan* plan) {
+  plan->ndim = graphs[0]->ndim;
+  std::vector<I8Args> inst((size_t)n_inst);
+  std::vector<std::pair<int64_t, BatchItem>> items;
+  size_t lds = 0;
+  for (int k = 0; k < n_inst; ++k) {
+    const ising_graph* g = graphs[k];
+    const SweepLaunch& s = launches[k];
+    const Lattice& L = g->lat;
+    const int block = sweep_i8_block(L, kMaxBlock);
+    if (block <= 0) return hipErrorInvalidValue;
+    I8Args& a = inst[(size_t)k];
+    a.lat = L;
+    a.wbits = g->d_wbits;
+    a.spins = s.spins;
+    a.thr = s.d_thr;
+    a.cut = s.cut;
+    a.energy = s.energy;
+    a.flips = s.flips;
+    a.stats = nullptr;
+    a.seed = s.seed;
+    a.w_total = g->w_total;
+    a.n_replicas = s.n_replicas;
+    a.replica_offset = s.replica_offset;
+    a.t_begin = s.t_begin;
+    a.t_end = s.t_end;
+    a.init = s.init;
+    a.lp = block / L.hx;
+    const size_t b = sweep_i8_lds_bytes(L);
+    if (b > lds) lds = b;
+    const int64_t cost = (int64_t)L.n * (s.t_end - s.t_begin);
+    for (int r0 = 0; r0 < s.n_replicas; r0 += 4) items.push_back({cost * std::min(4, s.n_replicas - r0), BatchItem{k, r0}});
+  }
+  // costliest first; ties in instance and replica order
+  std::stable_sort(items.begin(), items.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  std::vector<BatchItem> order(items.size());
+  for (size_t i = 0; i < items.size(); ++i) order[i] = items[i].second;
+  plan->n_items = (int)order.size();
+  plan->lds = lds;
+  plan->block = kMaxBlock;
+  const void* kernel = plan->ndim == 2 ? (const void*)k_sweep_i8_batch<2> : (const void*)k_sweep_i8_batch<3>;
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, dev = 0, cus = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kMaxBlock, lds);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  plan->grid = std::min(plan->n_items, per_cu * cus);
+  e = hipMalloc(&plan->d_inst, sizeof(I8Args) * (size_t)n_inst);
+  if (e == hipSuccess) e = hipMalloc(&plan->d_items, sizeof(BatchItem) * order.size());
+  if (e == hipSuccess) e = hipMalloc((void**)&plan->d_counter, sizeof(unsigned int));
+  if (e == hipSuccess) e = hipMemcpy(plan->d_inst, inst.data(), sizeof(I8Args) * (size_t)n_inst, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(plan->d_items, order.data(), sizeof(BatchItem) * order.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+hipError_t run_i8_batch(const I8BatchPlan& plan, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, stream, plan.d_counter);
+  if (plan.ndim == 2)
+    hipLaunchKernelGGL(k_sweep_i8_batch<2>, dim3(plan.grid), dim3(plan.block), plan.lds, stream,
+                       (const I8Args*)plan.d_inst, (const BatchItem*)plan.d_items, plan.n_items, plan.d_counter);
+  else
+    hipLaunchKernelGGL(k_sweep_i8_batch<3>, dim3(plan.grid), dim3(plan.block), plan.lds, stream,
+                       (const I8Args*)plan.d_inst, (const BatchItem*)plan.d_items, plan.n_items, plan.d_counter);
+  return hipGetLastError();
+}
+
+void free_i8_batch(I8BatchPlan& plan) {
+  (void)hipFree(plan.d_inst);
+  (void)hipFree(plan.d_items);
+  (void)hipFree(plan.d_counter);
+  plan.d_inst = plan.d_items = nullptr;
+  plan.d_counter = nullptr;
 }
 
 }  // namespace ising

@@ -1,0 +1,151 @@
+"""Time-to-target of learned culling against the plain all-trials run.
+
+Protocol (20,000-spin torus 100 x 200, weight seed 81, R = 8,192 replicas,
+S = 40,000 sweeps, geometric beta 0.05 -> 4.0, checkpoints every 2,000
+sweeps):
+ 1. training rows: plain runs on other instances (weight seeds 1001..1013),
+    features at the 19 checkpoints of the first 100,000 trajectories,
+    labelled with their end-of-trial cut / |E|;
+ 2. train the 16-64-64-1 network (Adam, lr 1e-3, batch 8,192, 20 epochs);
+ 3. for run seeds 201..205: plain, learned-cull and energy-cull runs;
+ 4. best = largest cut of any run, including one longer plain run;
+    target = ceil(0.999 best) (Table I's 99.9% rule);
+ 5. per run: P_s, r (eq. (3)), STT (eq. (4)), TTT (eq. (5)) with
+    t_trial = batch time / R; medians over the seeds per method.
+Clones are correlated, so eq. (3)'s independence assumption flatters the
+culled forms' P_s; the first-hit times (earliest checkpoint whose best cut
+reaches the target) are reported beside it.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import create_graph
+from . import learn, metrics
+
+
+def run_method(g, method, seed, R, S, window, model, log):
+    """One batch; returns end-of-trial cuts, batch seconds, and the best cut
+    at the end of every window (for first-hit times)."""
+    window_best = []
+    out = learn.anneal(g, R, S, seed, "geometric", 0.05, 4.0, window, method, model,
+                       on_window=lambda k, end, cut: window_best.append((end, cut.max())))
+    cuts = out["cut"].cpu().numpy()
+    window_best = [(end, int(m.item())) for end, m in window_best]
+    log("  %-7s seed %d: %.3f s, best %d, mean %.1f" % (method, seed, out["seconds"], cuts.max(), cuts.mean()))
+    return cuts, out["seconds"], window_best
+
+
+def first_hit_seconds(window_best, target, S, seconds):
+    """Batch time up to the first window end whose best cut reaches the
+    target (time taken as proportional to sweeps), or None."""
+    for end, best in window_best:
+        if best >= target:
+            return seconds * end / S
+    return None
+
+
+def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000, run_seeds=(201, 202, 203, 204, 205),
+                   train_seeds=tuple(range(1001, 1014)), n_traj=100000, epochs=20, batch=8192, long_sweeps=200000,
+                   log=print):
+    import torch
+
+    t_start = time.time()
+    instances = [(list(dims), ws, 5000 + ws) for ws in train_seeds]
+    per_instance = len(learn.checkpoints(S, window))
+    X, Y = learn.trajectories(instances, R, S, window)
+    # keep the first n_traj trajectories (instance-major, then replica)
+    rows = []
+    for k in range(len(instances)):
+        take = min(R, max(0, n_traj - k * R))
+        if take == 0:
+            break
+        for c in range(per_instance):
+            base = (k * per_instance + c) * R
+            rows.append(torch.arange(base, base + take, device=X.device))
+    sel = torch.cat(rows)
+    X, Y = X[sel].contiguous(), Y[sel].contiguous()
+    log("training rows %d (%d trajectories x %d checkpoints), %.1f s" % (X.shape[0], X.shape[0] // per_instance,
+                                                                           per_instance, time.time() - t_start))
+    model, history = learn.train(X, Y, epochs=epochs, batch=batch, log=log)
+
+    g = create_graph(list(dims), weight_seed)
+    results = {m: [] for m in learn.METHODS}
+    all_best = []
+    for seed in run_seeds:
+        for method in learn.METHODS:
+            cuts, secs, wb = run_method(g, method, seed, R, S, window, model if method == "learned" else None, log)
+            results[method].append((seed, cuts, secs, wb))
+            all_best.append(int(cuts.max()))
+    long = learn.anneal(g, R, long_sweeps, 299, "geometric", 0.05, 4.0, window, "plain")
+    long_best = int(long["cut"].max().item())
+    log("  long plain run (%d sweeps): best %d, %.1f s" % (long_sweeps, long_best, long["seconds"]))
+    compared_best = max(all_best)
+    summary = {"n_edges": g.n_edges, "long_run_best": long_best, "compared_runs_best": compared_best, "targets": {}}
+    # two readings of "the best cut found for the instance": the best of the
+    # compared runs (every method sees the same target), and that together
+    # with one much longer plain run
+    for tname, best in (("compared_runs", compared_best), ("with_long_run", max(compared_best, long_best))):
+        target = metrics.target_cut(best)
+        block = {"best_cut": best, "target": target, "methods": {}}
+        for method in learn.METHODS:
+            per = [learn.time_to_target(c, target, S, s) for _, c, s, _ in results[method]]
+            hits = [first_hit_seconds(wb, target, S, s) for _, _, s, wb in results[method]]
+            reached = [h for h in hits if h is not None]
+            block["methods"][method] = {
+                "median_TTT_s": learn.median([p["TTT"] for p in per]),
+                "median_STT_sweeps": learn.median([p["STT"] for p in per]),
+                "P_s": [p["P_s"] for p in per],
+                "first_hit_seconds": hits,
+                "median_first_hit_s": learn.median(reached) if reached else None,
+                "runs_reaching_target": len(reached),
+            }
+        pl = block["methods"]["plain"]["median_TTT_s"]
+        le = block["methods"]["learned"]["median_TTT_s"]
+        block["learned_over_plain_TTT"] = (le / pl) if (math.isfinite(pl) and math.isfinite(le) and pl > 0) else None
+        summary["targets"][tname] = block
+    summary["runs"] = {m: [{"seed": sd, "batch_seconds": s, "best": int(c.max()), "mean": float(c.mean()),
+                            "cut_values": [int(v) for v in np.unique(c, return_counts=True)[0]],
+                            "cut_counts": [int(v) for v in np.unique(c, return_counts=True)[1]]}
+                           for sd, c, s, _ in results[m]] for m in learn.METHODS}
+    summary["train_loss"] = history
+    summary["config"] = dict(dims=list(dims), weight_seed=weight_seed, R=R, S=S, window=window, run_seeds=list(run_seeds),
+                             train_seeds=list(train_seeds), n_traj=n_traj, epochs=epochs, batch=batch,
+                             long_sweeps=long_sweeps)
+    summary["wall_seconds"] = time.time() - t_start
+    g.close()
+    return summary
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="learned culling vs plain: time to 99.9% of the best cut")
+    ap.add_argument("--replicas", type=int, default=8192)
+    ap.add_argument("--sweeps", type=int, default=40000)
+    ap.add_argument("--window", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--train-instances", type=int, default=13)
+    ap.add_argument("--n-traj", type=int, default=100000)
+    ap.add_argument("--seeds", type=int, default=5)
+    ap.add_argument("--long-sweeps", type=int, default=200000)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    s = ttt_experiment(R=args.replicas, S=args.sweeps, window=args.window, epochs=args.epochs,
+                       train_seeds=tuple(range(1001, 1001 + args.train_instances)), n_traj=args.n_traj,
+                       run_seeds=tuple(range(201, 201 + args.seeds)), long_sweeps=args.long_sweeps, log=log)
+    text = json.dumps(s)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text + "\n")
+    print(text)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -46,13 +46,14 @@ def checkpoints(n_sweeps, window):
 
 
 def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, beta1=4.0, window=2000,
-           method="plain", model=None, layout="auto", on_checkpoint=None, stream=None):
+           method="plain", model=None, layout="auto", on_checkpoint=None, on_window=None, stream=None):
     """One batch of R trials of S sweeps.  method: plain | learned | energy.
 
     Returns dict(spins, cut, energy, orders, seconds) with device tensors;
     `orders` lists each checkpoint's ranking (device int32 [R]) when culling;
     `on_checkpoint(k, sweeps_done, feats)` is called with each checkpoint's
-    features (plain and learned forms compute them)."""
+    features (plain and learned forms compute them); `on_window(k, end, cut)`
+    with the cuts at the end of every window (before any culling)."""
     import torch
 
     if method not in METHODS:
@@ -79,6 +80,8 @@ def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, 
     for k, end in enumerate(cps + [n_sweeps]):
         run_trials(graph, spins, seed, n_sweeps, begin, end, schedule, beta0, beta1, None, begin == 0, layout,
                    cut, energy, flips, stream=st)
+        if on_window is not None:
+            on_window(k, end, cut)
         if end < n_sweeps:
             if want_features:
                 beta = schedule_beta(n_sweeps, end - 1, schedule, beta0, beta1)

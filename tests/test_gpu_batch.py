@@ -1,0 +1,147 @@
+"""Persistent batches of uneven instances: every replica bit-identical to a
+single-instance run (itself pinned to the oracle), at small and full size,
+eagerly and replayed from a captured HIP graph."""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ising():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_18508_amd as m
+
+    m.lib()
+    return m
+
+
+def make_runs(ising, specs):
+    import torch
+
+    graphs, runs = [], []
+    for dims, wseed, seed, R, S, b, e, sched, b0, b1 in specs:
+        g = ising.create_graph(dims, wseed)
+        graphs.append(g)
+        runs.append(dict(seed=seed, n_sweeps=S, sweep_begin=b, sweep_end=e, schedule=sched, beta0=b0, beta1=b1,
+                         spins=torch.zeros((R, g.n), dtype=torch.int8, device="cuda"),
+                         cut=torch.zeros(R, dtype=torch.int64, device="cuda"),
+                         energy=torch.zeros(R, dtype=torch.int64, device="cuda"),
+                         flips=torch.zeros(R, dtype=torch.int32, device="cuda")))
+    return graphs, runs
+
+
+def single(ising, g, run):
+    import torch
+
+    R = run["spins"].shape[0]
+    spins = torch.zeros_like(run["spins"])
+    cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+    en = torch.zeros(R, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(R, dtype=torch.int32, device="cuda")
+    ising.run_trials(g, spins, run["seed"], run["n_sweeps"], run["sweep_begin"], run["sweep_end"], run["schedule"],
+                     run["beta0"], run["beta1"], None, True, "i8", cut, en, fl)
+    return spins, cut, en, fl
+
+
+def assert_run_equal(run, ref):
+    for name, r in zip(("spins", "cut", "energy", "flips"), ref):
+        assert bool((run[name] == r).all()), name
+
+
+SMALL = [([6, 8], 1, 11, 13, 300, 0, 300, "geometric", 0.05, 4.0),
+         ([10, 12], 2, 12, 5, 500, 0, 120, "linear", 0.1, 3.0),
+         ([20, 30], 3, 13, 40, 200, 0, 200, "geometric", 0.05, 4.0),
+         ([12, 16], 4, 14, 8, 800, 0, 800, "linear", 0.2, 2.5),
+         ([2, 4], 5, 15, 3, 100, 0, 100, "geometric", 0.1, 2.0)]
+
+
+def test_small_uneven_batch_matches_single_runs_and_oracle(ising):
+    import torch
+
+    graphs, runs = make_runs(ising, SMALL)
+    b = ising.Batch(graphs, runs)
+    assert b.n_items == sum((R + 3) // 4 for _, _, _, R, *_ in SMALL)
+    b.run()
+    torch.cuda.synchronize()
+    for g, run in zip(graphs, runs):
+        assert_run_equal(run, single(ising, g, run))
+    # and the first instance against the oracle directly
+    dims, wseed, seed, R, S = SMALL[0][:5]
+    n = oracle.n_sites(dims)
+    ref, fl = oracle.run(dims, oracle.random_weights(wseed, 2 * n), seed, R, S, schedule=oracle.SCHED_GEOMETRIC,
+                         beta0=0.05, beta1=4.0)
+    assert (runs[0]["spins"].cpu().numpy() == ref).all()
+    assert (runs[0]["flips"].cpu().numpy().astype(np.uint32) == fl).all()
+    b.close()
+
+
+def test_full_size_uneven_batch_matches_single_runs(ising):
+    """The four tori of 5,000-20,000 spins with 256-4,096 replicas and
+    5,000-20,000 sweeps in one persistent launch."""
+    import torch
+
+    specs = [([50, 100], 11, 111, 256, 5000, 0, 5000, "geometric", 0.05, 4.0),
+             ([100, 100], 12, 112, 1024, 10000, 0, 10000, "geometric", 0.05, 4.0),
+             ([100, 140], 13, 113, 2048, 15000, 0, 15000, "geometric", 0.05, 4.0),
+             ([100, 200], 14, 114, 4096, 20000, 0, 20000, "geometric", 0.05, 4.0)]
+    graphs, runs = make_runs(ising, specs)
+    b = ising.Batch(graphs, runs)
+    b.run()
+    torch.cuda.synchronize()
+    for g, run in zip(graphs, runs):
+        assert_run_equal(run, single(ising, g, run))
+    b.close()
+
+
+def test_graph_replays_match_eager(ising):
+    import torch
+
+    graphs, runs = make_runs(ising, SMALL)
+    b = ising.Batch(graphs, runs)
+    b.run()
+    torch.cuda.synchronize()
+    eager = [{k: run[k].clone() for k in ("spins", "cut", "energy", "flips")} for run in runs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.run()  # warm-up on the capture stream's side
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.run()
+    for replay in range(3):
+        for run in runs:  # eager work between replays: scramble the outputs
+            for k in ("spins", "cut", "energy", "flips"):
+                run[k].fill_(replay + 1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for run, ref in zip(runs, eager):
+            for k in ref:
+                assert bool((run[k] == ref[k]).all()), (replay, k)
+    b.close()
+
+
+def test_batch_argument_errors(ising):
+    import torch
+
+    g2 = ising.create_graph([6, 8], 1)
+    g3 = ising.create_graph([4, 4, 4], 1)
+    s2 = torch.zeros((4, g2.n), dtype=torch.int8, device="cuda")
+    s3 = torch.zeros((4, g3.n), dtype=torch.int8, device="cuda")
+    run = dict(seed=1, n_sweeps=10)
+    with pytest.raises(ising.IsingError) as e:
+        ising.Batch([g2, g3], [dict(run, spins=s2), dict(run, spins=s3)])
+    assert e.value.code == ising.E_ARG
+    with pytest.raises(ising.IsingError) as e:
+        ising.Batch([g2], [dict(run, spins=s2, layout="bp32")])
+    assert e.value.code == ising.E_UNSUPPORTED
+    with pytest.raises(ising.IsingError) as e:
+        ising.Batch([g2], [dict(run, spins=s2, sweep_begin=3, sweep_end=2)])
+    assert e.value.code == ising.E_ARG
