@@ -311,6 +311,15 @@ int ising_feature_stats(const float* x, int64_t rows, float* mean, float* std, v
 int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, int8_t* spins,
                      ising_track* track, int32_t* order_out, void* stream);
 
+/* The network is trained on the cut a replica still gains until the end of
+ * its trial, gain = (final cut - cut now) / |E|; its ranking score is the
+ * predicted final cut / |E| = cut now / |E| + gain, where
+ * cut now / |E| = (W_total / |E| - features[r][0]) / 2 (eq. (1)-(2)).
+ *   gain      device float [R] (network output);  features device float [R][16].
+ *   score     device float [R] (may alias gain).  Asynchronous. */
+int ising_final_cut_score(const ising_graph* g, const float* gain, const float* features, int64_t n_replicas,
+                          float* score, void* stream);
+
 /* score[r] = -energy[r] (the energy-ranked baseline of culling). */
 int ising_energy_score(const int64_t* energy, int64_t n_replicas, float* score, void* stream);
 

@@ -151,3 +151,9 @@ def cull_clone(order, spins, track=None):
         if track is not None:
             for key in track:
                 track[key][dst] = track[key][src]
+
+
+def final_cut_score(w_total, n_edges, gain, feats):
+    """Predicted final cut / |E| = cut now / |E| + gain, with
+    cut now = (W_total - H) / 2 and feature 0 = H / |E|."""
+    return 0.5 * (w_total / n_edges - np.asarray(feats, np.float64)[:, 0]) + np.asarray(gain, np.float64)

@@ -31,7 +31,7 @@ EXPORTED = [
     "ising_philox_dump", "ising_last_error",
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
-    "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy",
+    "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy", "ising_final_cut_score",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -102,6 +102,7 @@ def lib():
         L.ising_batch_info.argtypes = [vp, vp, vp, vp, vp]
         L.ising_batch_destroy.argtypes = [vp]
         L.ising_batch_destroy.restype = None
+        L.ising_final_cut_score.argtypes = [vp, vp, vp, i64, vp, vp]
         for name in EXPORTED:
             if name not in ("ising_destroy_graph", "ising_last_error", "ising_mlp_workspace_floats",
                             "ising_batch_destroy"):
@@ -313,6 +314,12 @@ def feature_stats(x, mean, std, rows=None, stream=None):
 def cull_clone(score, spins, track=None, order=None, stream=None):
     R, n = spins.shape
     _check(lib().ising_cull_clone(_ptr(score), R, n, _ptr(spins), _ptr(track), _ptr(order), _stream(stream)))
+
+
+def final_cut_score(graph, gain, feats, score, stream=None):
+    """score = predicted final cut / |E| from the network's gain prediction."""
+    _check(lib().ising_final_cut_score(graph.handle, _ptr(gain), _ptr(feats), gain.shape[0], _ptr(score),
+                                       _stream(stream)))
 
 
 def energy_score(energy, score, stream=None):

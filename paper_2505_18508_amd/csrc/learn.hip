@@ -399,6 +399,11 @@ __global__ void k_clone(const int32_t* order, int n_rep, int64_t n, int8_t* spin
   if (track && blockIdx.x == 0 && threadIdx.x == 0) track[dst] = track[src];
 }
 
+__global__ void k_final_cut_score(const float* gain, const float* feat, int64_t n, double w_over_e, float* score) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) score[i] = (float)(0.5 * (w_over_e - (double)feat[i * NF]) + (double)gain[i]);
+}
+
 __global__ void k_energy_score(const int64_t* energy, int64_t n, float* score) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) score[i] = -(float)energy[i];
@@ -550,6 +555,19 @@ int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, in
   }
   if (!order_out) (void)hipFreeAsync(order, st);
   return e == hipSuccess ? ISING_OK : fail_hip(e, "cull launch");
+}
+
+int ising_final_cut_score(const ising_graph* g, const float* gain, const float* features, int64_t n_replicas,
+                          float* score, void* stream) {
+  if (!g) return fail(ISING_E_ARG, "graph is NULL");
+  if (n_replicas < 0) return fail(ISING_E_ARG, "n_replicas < 0");
+  if (n_replicas == 0) return ISING_OK;
+  if (!gain || !features || !score) return fail(ISING_E_ARG, "NULL buffer");
+  const double w_over_e = (double)g->w_total / (double)g->n_edges;
+  hipLaunchKernelGGL(ising::k_final_cut_score, dim3((unsigned)((n_replicas + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, gain, features, n_replicas, w_over_e, score);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ISING_OK : fail_hip(e, "final cut score launch");
 }
 
 int ising_energy_score(const int64_t* energy, int64_t n_replicas, float* score, void* stream) {

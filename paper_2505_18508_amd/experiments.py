@@ -51,13 +51,13 @@ def first_hit_seconds(window_best, target, S, seconds):
 
 def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000, run_seeds=(201, 202, 203, 204, 205),
                    train_seeds=tuple(range(1001, 1014)), n_traj=100000, epochs=20, batch=8192, long_sweeps=200000,
-                   log=print):
+                   label="final", log=print):
     import torch
 
     t_start = time.time()
     instances = [(list(dims), ws, 5000 + ws) for ws in train_seeds]
     per_instance = len(learn.checkpoints(S, window))
-    X, Y = learn.trajectories(instances, R, S, window)
+    X, Y = learn.trajectories(instances, R, S, window, label=label)
     # keep the first n_traj trajectories (instance-major, then replica)
     rows = []
     for k in range(len(instances)):
@@ -71,9 +71,12 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
     X, Y = X[sel].contiguous(), Y[sel].contiguous()
     log("training rows %d (%d trajectories x %d checkpoints), %.1f s" % (X.shape[0], X.shape[0] // per_instance,
                                                                            per_instance, time.time() - t_start))
-    model, history = learn.train(X, Y, epochs=epochs, batch=batch, log=log)
+    model, history = learn.train(X, Y, epochs=epochs, batch=batch, log=log, label=label)
 
     g = create_graph(list(dims), weight_seed)
+    for method in learn.METHODS:  # untimed warm-up of every code path
+        learn.anneal(g, R, min(S, 2 * window), 1, "geometric", 0.05, 4.0, window, method,
+                     model if method == "learned" else None)
     results = {m: [] for m in learn.METHODS}
     all_best = []
     for seed in run_seeds:
@@ -115,7 +118,7 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
     summary["train_loss"] = history
     summary["config"] = dict(dims=list(dims), weight_seed=weight_seed, R=R, S=S, window=window, run_seeds=list(run_seeds),
                              train_seeds=list(train_seeds), n_traj=n_traj, epochs=epochs, batch=batch,
-                             long_sweeps=long_sweeps)
+                             long_sweeps=long_sweeps, label=label)
     summary["wall_seconds"] = time.time() - t_start
     g.close()
     return summary
@@ -132,12 +135,16 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=5)
     ap.add_argument("--long-sweeps", type=int, default=200000)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--label", choices=learn.LABELS, default="final")
+    ap.add_argument("--dims", default="100x200")
+    ap.add_argument("--weight-seed", type=int, default=81)
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
-    s = ttt_experiment(R=args.replicas, S=args.sweeps, window=args.window, epochs=args.epochs,
+    dims = tuple(int(v) for v in args.dims.split("x"))
+    s = ttt_experiment(dims=dims, weight_seed=args.weight_seed, label=args.label, R=args.replicas, S=args.sweeps, window=args.window, epochs=args.epochs,
                        train_seeds=tuple(range(1001, 1001 + args.train_instances)), n_traj=args.n_traj,
                        run_seeds=tuple(range(201, 201 + args.seeds)), long_sweeps=args.long_sweeps, log=log)
     text = json.dumps(s)

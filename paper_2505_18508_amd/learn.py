@@ -2,8 +2,9 @@
 
 A trial (paper, Section III) is a run of S sweeps read out at its end.  Here
 R trials run together and, every `window` sweeps, each replica's trajectory
-features go through a small network that predicts its end-of-trial cut; the
-lower half of the replicas is replaced by copies of the upper half.  Every
+features go through a small network that predicts the cut the replica will
+still gain by the end of its trial; current cut plus predicted gain ranks the
+replicas, and the lower half is replaced by copies of the upper half.  Every
 replica keeps its own Philox stream, so copies diverge at once.  The plain
 form (no culling) runs the same windows and is what the learned form is
 judged against, with eq. (3)-(5) applied to both.
@@ -16,28 +17,37 @@ import time
 
 import numpy as np
 
-from . import (adam_step, create_graph, cull_clone, energy_score, feature_stats, features, mlp_forward, mlp_init,
-               mlp_loss_grad, mlp_workspace_floats, new_track, run_trials, schedule_beta)
+from . import (adam_step, create_graph, cull_clone, energy_score, feature_stats, features, final_cut_score,
+               mlp_forward, mlp_init, mlp_loss_grad, mlp_workspace_floats, new_track, run_trials, schedule_beta)
 from . import metrics
 
 METHODS = ("plain", "learned", "energy")
 
 
-class Model:
-    """Network parameters and the feature normalisation they were trained with."""
+LABELS = ("final", "gain")
 
-    def __init__(self, params, mean, std):
-        self.params, self.mean, self.std = params, mean, std
+
+class Model:
+    """Network parameters, the feature normalisation they were trained with,
+    and what the output means: "final" = end-of-trial cut / |E|; "gain" = cut
+    still to come / |E| (the score adds the current cut back)."""
+
+    def __init__(self, params, mean, std, label="final"):
+        if label not in LABELS:
+            raise ValueError("label must be one of %s" % (LABELS,))
+        self.params, self.mean, self.std, self.label = params, mean, std, label
 
     def save(self, path):
-        np.savez(path, params=self.params.cpu().numpy(), mean=self.mean.cpu().numpy(), std=self.std.cpu().numpy())
+        np.savez(path, params=self.params.cpu().numpy(), mean=self.mean.cpu().numpy(), std=self.std.cpu().numpy(),
+                 label=np.array(LABELS.index(self.label)))
 
     @classmethod
     def load(cls, path, device="cuda"):
         import torch
 
         with np.load(path, allow_pickle=False) as z:
-            return cls(*(torch.from_numpy(z[k]).to(device) for k in ("params", "mean", "std")))
+            arrs = [torch.from_numpy(z[k]).to(device) for k in ("params", "mean", "std")]
+            return cls(*arrs, label=LABELS[int(z["label"])])
 
 
 def checkpoints(n_sweeps, window):
@@ -92,6 +102,8 @@ def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, 
             if method != "plain":
                 if method == "learned":
                     mlp_forward(model.params, feats, score, mean=model.mean, std=model.std, stream=st)
+                    if model.label == "gain":
+                        final_cut_score(graph, score, feats, score, stream=st)
                 else:
                     energy_score(energy, score, stream=st)
                 order = torch.empty(R, dtype=torch.int32, device=dev)
@@ -104,26 +116,31 @@ def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, 
 
 
 def trajectories(instances, n_replicas, n_sweeps, window, schedule="geometric", beta0=0.05, beta1=4.0,
-                 layout="auto"):
+                 layout="auto", label="final"):
     """Training rows from plain runs: features at every checkpoint, labelled
-    with the replica's end-of-trial cut / |E|.  instances: [(dims, weight_seed,
-    run_seed)].  Returns device tensors X [N][16], Y [N]."""
+    with the end-of-trial cut / |E| (label "final") or with the cut still to
+    come, (final cut - cut at the checkpoint) / |E| (label "gain").
+    instances: [(dims, weight_seed, run_seed)].  Returns device tensors
+    X [N][16], Y [N]."""
     import torch
 
     xs, ys = [], []
     for dims, wseed, rseed in instances:
         g = create_graph(dims, wseed)
-        rows = []
+        rows, cuts = [], {}
         out = anneal(g, n_replicas, n_sweeps, rseed, schedule, beta0, beta1, window, "plain", layout=layout,
-                     on_checkpoint=lambda k, e, f: rows.append(f.clone()))
-        label = out["cut"].to(torch.float32) / float(g.n_edges)
+                     on_checkpoint=lambda k, e, f: rows.append(f.clone()),
+                     on_window=lambda k, e, c: cuts.__setitem__(k, c.clone()))
+        final = out["cut"]
         xs.extend(rows)
-        ys.extend([label] * len(rows))
+        for k in range(len(rows)):
+            y = final - cuts[k] if label == "gain" else final
+            ys.append(y.to(torch.float32) / float(g.n_edges))
         g.close()
     return torch.cat(xs), torch.cat(ys)
 
 
-def train(X, Y, epochs=20, batch=8192, lr=1e-3, seed=3, log=None):
+def train(X, Y, epochs=20, batch=8192, lr=1e-3, seed=3, log=None, label="final"):
     """Adam on the mean squared error, with the library's forward/backward
     kernels; deterministic given the seed (fixed shuffles, fixed-order
     reductions).  Returns (Model, per-epoch mean losses)."""
@@ -156,7 +173,7 @@ def train(X, Y, epochs=20, batch=8192, lr=1e-3, seed=3, log=None):
         history.append(sum(losses) / N)
         if log:
             log("epoch %d loss %.6g" % (epoch, history[-1]))
-    return Model(params, mean, std), history
+    return Model(params, mean, std, label), history
 
 
 def time_to_target(cuts, target, n_sweeps, seconds):

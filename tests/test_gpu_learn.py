@@ -235,3 +235,16 @@ def test_culled_trajectory_replays_on_oracle(ising, method):
     if method == "energy":
         # the energy-ranked form keeps the lowest-energy replicas at each checkpoint
         assert all(sorted(o.tolist()) == list(range(R)) for o in orders)
+
+
+def test_final_cut_score_matches_oracle(ising):
+    import torch
+
+    rng = np.random.default_rng(12)
+    g = ising.create_graph([20, 30], 7)
+    gain = rng.standard_normal(50).astype(np.float32) * 1e-3
+    feats = rng.standard_normal((50, 16)).astype(np.float32)
+    score = torch.zeros(50, dtype=torch.float32, device="cuda")
+    ising.final_cut_score(g, dev_tensor(gain), dev_tensor(feats), score)
+    ref = olearn.final_cut_score(g.w_total, g.n_edges, gain, feats)
+    assert np.allclose(score.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
