@@ -65,7 +65,9 @@ enum { ISING_SCHED_LINEAR = 0, ISING_SCHED_GEOMETRIC = 1, ISING_SCHED_TABLE = 2 
 enum {
   ISING_LAYOUT_AUTO = 0,  /* library chooses (autotuned where a tuning exists)  */
   ISING_LAYOUT_I8 = 1,    /* 4 replicas per 32-bit word: spin + maintained field */
-  ISING_LAYOUT_BP32 = 2   /* 32 replicas per 32-bit word: one spin bit each      */
+  ISING_LAYOUT_BP32 = 2,  /* 32 replicas per 32-bit word: one spin bit each      */
+  ISING_LAYOUT_STREAM = 3 /* 32 replicas per word, state in HBM, one launch per  */
+                          /* colour half-sweep (lattices too large for LDS)      */
 };
 
 /* A cut or energy that could not be computed because the replica's spins

@@ -389,7 +389,15 @@ int check_run(const ising_graph* g, const ising_run_params* p, const int8_t* spi
     // 32 replicas per block wins per attempt, but only fills the chip with at
     // least one group per compute unit
     const int64_t groups = ((int64_t)p->n_replicas + 31) / 32;
-    layout = (bp_fits && (groups >= dev.cus || !i8_fits)) ? ISING_LAYOUT_BP32 : ISING_LAYOUT_I8;
+    if (!i8_fits && !bp_fits)
+      layout = ISING_LAYOUT_STREAM;
+    else
+      layout = (bp_fits && (groups >= dev.cus || !i8_fits)) ? ISING_LAYOUT_BP32 : ISING_LAYOUT_I8;
+  }
+  if (layout == ISING_LAYOUT_STREAM) {
+    if (g->lat.hx < 1) return fail(ISING_E_UNSUPPORTED, "torus too small");
+    *layout_out = layout;
+    return ISING_OK;
   }
   if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32) return fail(ISING_E_ARG, "unknown layout %d", p->layout);
   if ((layout == ISING_LAYOUT_I8 && !i8_fits) || (layout == ISING_LAYOUT_BP32 && !bp_fits))
@@ -440,7 +448,26 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
   rc = threshold_table(g, p, st, &d_thr, &owned);
   if (rc) return rc;
   const ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
-  hipError_t e = layout == ISING_LAYOUT_BP32 ? ising::launch_sweep_bp32(g, s, st) : ising::launch_sweep_i8(g, s, st);
+  hipError_t e;
+  if (layout == ISING_LAYOUT_STREAM) {
+    // stream-ordered working state: the words of every 32-replica group and their input flags
+    const size_t wbytes = ising::stream_words_bytes(g->lat, p->n_replicas);
+    const size_t groups = ((size_t)p->n_replicas + 31) / 32;
+    uint32_t* words = nullptr;
+    uint32_t* bad = nullptr;
+    e = hipMallocAsync((void**)&words, wbytes, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&bad, sizeof(uint32_t) * groups, st);
+    if (e != hipSuccess) {
+      if (words) (void)hipFreeAsync(words, st);
+      if (owned) (void)hipFreeAsync(d_thr, st);
+      return fail(ISING_E_NOMEM, "streamed state (%zu bytes): %s", wbytes, hipGetErrorString(e));
+    }
+    e = ising::launch_sweep_stream(g, s, words, bad, st);
+    (void)hipFreeAsync(words, st);
+    (void)hipFreeAsync(bad, st);
+  } else {
+    e = layout == ISING_LAYOUT_BP32 ? ising::launch_sweep_bp32(g, s, st) : ising::launch_sweep_i8(g, s, st);
+  }
   if (owned) (void)hipFreeAsync(d_thr, st);
   if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");
   return ISING_OK;

@@ -1,0 +1,267 @@
+// Checkerboard Metropolis sweeps for lattices too large for one block's LDS:
+// 32 replicas per 32-bit word (as the on-chip bit-packed kernel), state in
+// HBM, one launch per colour half-sweep.  A colour-p launch only reads
+// colour-(1-p) words and only writes colour-p words, so the launch boundary
+// is the only synchronisation the checkerboard needs, and the result is the
+// sequential sweep's bit for bit.
+//
+// State: words [group][2][n/2] in colour-split order (word bit j = spin of
+// replica 32 g + j).  Per half-sweep a word costs its own read and write and
+// the reads of its neighbours' words (12 bytes per word per sweep, 0.375
+// bytes per spin-update attempt).
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace ising {
+namespace {
+
+constexpr int kStreamBlock = 256;
+
+struct StreamArgs {
+  Lattice lat;
+  const uint8_t* wbits;  // colour-split, bit d set: weight of direction d is -1
+  uint32_t* words;       // [groups][n]
+  const uint32_t* thr;
+  uint32_t* flips;       // [R] or null
+  unsigned long long* stats;
+  uint64_t seed;
+  int32_t n_replicas, replica_offset, groups;
+};
+
+template <int DEG>
+__device__ __forceinline__ void count_bonds(const uint32_t* x, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+  if (DEG == 4) {
+    const uint32_t s1 = x[0] ^ x[1], c1 = x[0] & x[1];
+    const uint32_t s2 = x[2] ^ x[3], c2 = x[2] & x[3];
+    u0 = s1 ^ s2;
+    const uint32_t k = s1 & s2;
+    u1 = xor3(c1, c2, k);
+    u2 = (c1 & c2) | (k & (c1 | c2));
+  } else {
+    const uint32_t s1 = xor3(x[0], x[1], x[2]);
+    const uint32_t c1 = (x[0] & x[1]) | (x[2] & (x[0] | x[1]));
+    const uint32_t s2 = xor3(x[3], x[4], x[5]);
+    const uint32_t c2 = (x[3] & x[4]) | (x[5] & (x[3] | x[4]));
+    u0 = s1 ^ s2;
+    const uint32_t k = s1 & s2;
+    u1 = xor3(c1, c2, k);
+    u2 = (c1 & c2) | (k & (c1 | c2));
+  }
+}
+
+template <int NDIM, bool STATS>
+__global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a, int p, int t) {
+  constexpr int DEG = 2 * NDIM;
+  const Lattice& L = a.lat;
+  const int g = blockIdx.y;
+  const uint32_t h = blockIdx.x * kStreamBlock + threadIdx.x;
+  const int r0 = 32 * g;
+  const int nvalid = min(32, a.n_replicas - r0);
+  uint32_t F = 0u;
+  uint32_t n_draws = 0u;
+  const uint32_t* tr = a.thr + (size_t)t * NDIM;
+  const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
+  if (h < (uint32_t)L.half) {
+    const uint32_t hx = (uint32_t)L.hx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz;
+    const uint32_t line = h / hx;  // one division per thread and launch
+    const uint32_t m = h - line * hx;
+    const uint32_t z = NDIM == 2 ? 0u : line / Ly;
+    const uint32_t y = line - z * Ly;
+    const uint32_t o = (p + y + z) & 1u;
+    uint32_t* w = a.words + (size_t)g * L.n;
+    const uint32_t own = (uint32_t)p * (uint32_t)L.half + h;
+    const uint32_t base = (uint32_t)(1 - p) * (uint32_t)L.half + line * hx;  // same line, other colour
+    const uint32_t plane = hx * Ly;
+    uint32_t nb[DEG];
+    nb[0] = base + (o ? (m + 1u == hx ? 0u : m + 1u) : m);
+    nb[1] = base + (o ? m : (m == 0u ? hx - 1u : m - 1u));
+    nb[2] = (y + 1u == Ly) ? base + m + hx - plane : base + m + hx;
+    nb[3] = (y == 0u) ? base + m + plane - hx : base + m - hx;
+    if (NDIM == 3) {
+      nb[DEG - 2] = (z + 1u == Lz) ? base + m - (Lz - 1u) * plane : base + m + plane;
+      nb[DEG - 1] = (z == 0u) ? base + m + (Lz - 1u) * plane : base + m - plane;
+    }
+    const uint32_t s = w[own];
+    const uint32_t wb = a.wbits[own];
+    uint32_t x[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+      const uint32_t plus = ((wb >> d) & 1u) ? 0u : 0xFFFFFFFFu;  // all ones iff w = +1
+      x[d] = xor3(s, w[nb[d]], plus);                              // unsatisfied bonds
+    }
+    uint32_t u0, u1, u2;
+    count_bonds<DEG>(x, u0, u1, u2);
+    uint32_t acc, k1, k2, k3 = 0u;
+    if (NDIM == 2) {
+      acc = u1 | u2;
+      k1 = u0 & ~acc;
+      k2 = ~(u0 | acc);
+    } else {
+      acc = u2 | (u1 & u0);
+      k1 = u1 & ~u0 & ~u2;
+      k2 = u0 & ~u1 & ~u2;
+      k3 = ~(u0 | u1 | u2);
+    }
+    uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
+    if (T1 != 0u) {
+      const uint32_t ci = line * (uint32_t)L.Lx + 2u * m + o;
+      const uint32_t quad0 = (uint32_t)(a.replica_offset + r0) >> 2;
+#pragma unroll
+      for (int q = 7; q >= 0; --q) {
+        const u32x4 r = philox_lane_c0(a.seed, ci, (uint32_t)t, quad0 + (uint32_t)q, kTagMetropolis);
+#pragma unroll
+        for (int b = 3; b >= 0; --b) {
+          c1 = 2u * c1 + (r.v[b] < T1 ? 1u : 0u);
+          c2 = 2u * c2 + (r.v[b] < T2 ? 1u : 0u);
+          if (NDIM == 3) c3 = 2u * c3 + (r.v[b] < T3 ? 1u : 0u);
+        }
+      }
+      if (STATS) {
+        const uint32_t lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
+        n_draws = __popc((k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & lanes);
+      }
+    }
+    F = acc | (k1 & c1) | (k2 & c2) | (k3 & c3);
+    if (F) w[own] = s ^ F;
+  }
+  if (STATS) {  // per-wave totals: Philox blocks (8 per word) and draws
+    const uint32_t words_here = (uint32_t)__popcll(__ballot(h < (uint32_t)L.half && T1 != 0u));
+    uint32_t d = n_draws;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    if ((threadIdx.x & 63) == 0 && words_here) {
+      atomicAdd(&a.stats[0], 8ull * words_here);
+      atomicAdd(&a.stats[1], (unsigned long long)d);
+    }
+  }
+  // flips per replica: one ballot per replica bit, added by lane 0 of the wave
+  if (a.flips) {
+    const bool lane0 = (threadIdx.x & 63) == 0;
+    for (int j = 0; j < nvalid; ++j) {
+      const uint32_t c = (uint32_t)__popcll(__ballot((F >> j) & 1u));
+      if (lane0 && c) atomicAdd(&a.flips[r0 + j], c);
+    }
+  }
+}
+
+// canonical int8 [R][n] <-> words [groups][n]; bad values flagged per replica
+__global__ void k_pack(Lattice L, const int8_t* spins, int32_t R, uint32_t* words, uint32_t* bad) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (i >= (uint32_t)L.n) return;
+  int p;
+  uint32_t h;
+  site_to_split(L, i, p, h);
+  const int r0 = 32 * g, nvalid = min(32, R - r0);
+  uint32_t word = 0u, flag = 0u;
+  for (int j = 0; j < nvalid; ++j) {
+    const int8_t v = spins[(size_t)(r0 + j) * L.n + i];
+    word |= (v > 0 ? 1u : 0u) << j;
+    flag |= (v != 1 && v != -1) ? (1u << j) : 0u;
+  }
+  words[(size_t)g * L.n + (uint32_t)p * (uint32_t)L.half + h] = word;
+  if (flag) atomicOr(&bad[g], flag);
+}
+
+__global__ void k_init_words(Lattice L, uint64_t seed, int32_t replica_offset, uint32_t* words) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (i >= (uint32_t)L.n) return;
+  int p;
+  uint32_t h;
+  site_to_split(L, i, p, h);
+  const uint32_t quad0 = (uint32_t)(replica_offset + 32 * g) >> 2;
+  uint32_t word = 0u;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const u32x4 u = philox_lane_c0(seed, i, 0u, quad0 + q, kTagInit);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) word |= (u.v[b] >> 31) << (4 * q + b);
+  }
+  words[(size_t)g * L.n + (uint32_t)p * (uint32_t)L.half + h] = word;
+}
+
+__global__ void k_unpack(Lattice L, const uint32_t* words, int32_t R, int8_t* spins) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (i >= (uint32_t)L.n) return;
+  int p;
+  uint32_t h;
+  site_to_split(L, i, p, h);
+  const uint32_t word = words[(size_t)g * L.n + (uint32_t)p * (uint32_t)L.half + h];
+  const int r0 = 32 * g, nvalid = min(32, R - r0);
+  for (int j = 0; j < nvalid; ++j) spins[(size_t)(r0 + j) * L.n + i] = ((word >> j) & 1u) ? (int8_t)1 : (int8_t)-1;
+}
+
+__global__ void k_zero_u32(uint32_t* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0u;
+}
+
+// replicas whose input held a value other than +/-1: cut and energy invalid
+__global__ void k_mark_invalid(const uint32_t* bad, int32_t R, int64_t* cut, int64_t* energy) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  if ((bad[r / 32] >> (r % 32)) & 1u) {
+    if (cut) cut[r] = INT64_MIN;
+    if (energy) energy[r] = INT64_MIN;
+  }
+}
+
+}  // namespace
+
+size_t stream_words_bytes(const Lattice& L, int n_replicas) {
+  return sizeof(uint32_t) * (size_t)L.n * (size_t)((n_replicas + 31) / 32);
+}
+
+hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint32_t* words, uint32_t* bad,
+                               hipStream_t stream) {
+  const Lattice& L = g->lat;
+  const int groups = (s.n_replicas + 31) / 32;
+  const dim3 site_grid((unsigned)((L.n + 255) / 256), (unsigned)groups);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, stream, bad, (int64_t)groups);
+  if (s.flips)
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((s.n_replicas + 255) / 256)), dim3(256), 0, stream, s.flips,
+                       (int64_t)s.n_replicas);
+  if (s.init)
+    hipLaunchKernelGGL(k_init_words, site_grid, dim3(256), 0, stream, L, s.seed, s.replica_offset, words);
+  else
+    hipLaunchKernelGGL(k_pack, site_grid, dim3(256), 0, stream, L, s.spins, s.n_replicas, words, bad);
+  StreamArgs a;
+  a.lat = L;
+  a.wbits = g->d_wbits;
+  a.words = words;
+  a.thr = s.d_thr;
+  a.flips = s.flips;
+  a.stats = s.stats;
+  a.seed = s.seed;
+  a.n_replicas = s.n_replicas;
+  a.replica_offset = s.replica_offset;
+  a.groups = groups;
+  const dim3 grid((unsigned)((L.half + kStreamBlock - 1) / kStreamBlock), (unsigned)groups);
+  for (int t = s.t_begin; t < s.t_end; ++t) {
+    for (int p = 0; p < 2; ++p) {
+      if (g->ndim == 2) {
+        if (s.stats) hipLaunchKernelGGL((k_halfsweep_stream<2, true>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
+        else hipLaunchKernelGGL((k_halfsweep_stream<2, false>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
+      } else {
+        if (s.stats) hipLaunchKernelGGL((k_halfsweep_stream<3, true>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
+        else hipLaunchKernelGGL((k_halfsweep_stream<3, false>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
+      }
+    }
+  }
+  hipLaunchKernelGGL(k_unpack, site_grid, dim3(256), 0, stream, L, words, s.n_replicas, s.spins);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (s.cut || s.energy) {
+    e = launch_cut_energy(g, s.spins, s.n_replicas, s.cut, s.energy, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mark_invalid, dim3((unsigned)((s.n_replicas + 255) / 256)), dim3(256), 0, stream, bad,
+                       s.n_replicas, s.cut, s.energy);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ising

@@ -1,0 +1,141 @@
+"""Autotuner for the sweep kernels.
+
+For a (torus, replica count) the tuner times every candidate launch shape on
+a short window of the real schedule: the packing (4 replicas per block with
+maintained fields, or 32 replicas per block bit-sliced) and the tile shape
+(lines of the colour-split lattice per pass, hence threads per block).
+Results never depend on the candidate -- the tuner checks that every
+candidate returns bit-identical spins, cuts, energies and flip counts --
+so only speed decides.  Choices are cached in a JSON file keyed by device,
+torus and replica count (ISING_TUNE_CACHE, default
+~/.cache/paper_2505_18508_amd/tune.json).
+"""
+import json
+import os
+
+from . import E_UNSUPPORTED, IsingError, run_trials
+
+MAX_BLOCK = 1024
+
+
+def _lattice(dims):
+    if len(dims) == 2:
+        return dict(Lz=1, Ly=dims[0], Lx=dims[1])
+    return dict(Lz=dims[0], Ly=dims[1], Lx=dims[2])
+
+
+def candidates(dims, n_replicas, cus=256):
+    """(layout, block_threads) pairs worth timing for a torus and R."""
+    L = _lattice(dims)
+    hx, lines = L["Lx"] // 2, L["Ly"] * L["Lz"]
+    out = []
+    if hx > MAX_BLOCK:
+        return out
+    max_lp = min(MAX_BLOCK // hx, lines)
+    lps = sorted({lp for lp in (max_lp, max_lp // 2, max_lp // 4, (max_lp // 2) * 2 if max_lp > 2 else max_lp)
+                  if lp >= 1})
+    for layout in ("i8", "bp32"):
+        if layout == "bp32" and (n_replicas + 31) // 32 < cus // 8:
+            continue  # fewer than one group per eight CUs: never competitive
+        for lp in lps:
+            out.append((layout, lp * hx))
+    return out
+
+
+def cache_path():
+    return os.environ.get("ISING_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2505_18508_amd", "tune.json"))
+
+
+def _key(device_name, dims, n_replicas):
+    return "%s|%s|%d" % (device_name, "x".join(str(d) for d in dims), n_replicas)
+
+
+def load_cache(path=None):
+    path = path or cache_path()
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def save_cache(cache, path=None):
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(graph, n_replicas, seed=1, n_sweeps=10000, window=100, schedule="geometric", beta0=0.05, beta1=4.0,
+         repeats=3, use_cache=True, path=None, log=None):
+    """Best (layout, block_threads) for this torus and R; times each candidate
+    on sweeps [0, window) of the schedule and checks they agree bit for bit."""
+    import torch
+
+    dev_name = torch.cuda.get_device_name()
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    key = _key(dev_name, graph.dims, n_replicas)
+    cache = load_cache(path) if use_cache else {}
+    if use_cache and key in cache:
+        c = cache[key]
+        return c["layout"], c["block_threads"]
+    cands = candidates(graph.dims, n_replicas, cus)
+    if not cands:
+        raise ValueError("no on-chip kernel fits this torus")
+    R = n_replicas
+    ref = None
+    results = []
+    for layout, bt in cands:
+        spins = torch.zeros((R, graph.n), dtype=torch.int8, device="cuda")
+        cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+        en = torch.zeros(R, dtype=torch.int64, device="cuda")
+        fl = torch.zeros(R, dtype=torch.int32, device="cuda")
+        run = lambda: run_trials(graph, spins, seed, n_sweeps, 0, window, schedule, beta0, beta1, None, True,
+                                 layout, cut, en, fl, bt)
+        try:
+            run()  # warm-up, and the candidate's result
+        except IsingError as e:
+            if e.code == E_UNSUPPORTED:  # does not fit on chip
+                continue
+            raise
+        torch.cuda.synchronize()
+        out = (spins.clone(), cut.clone(), en.clone(), fl.clone())
+        if ref is None:
+            ref = out
+        elif not all(bool(torch.equal(a, b)) for a, b in zip(ref, out)):
+            raise AssertionError("candidate %s/%d changed the results" % (layout, bt))
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(repeats):
+            run()
+        end.record()
+        end.synchronize()
+        ms = start.elapsed_time(end) / repeats
+        rate = R * graph.n * window / (ms / 1e3)
+        results.append((rate, layout, bt))
+        if log:
+            log("  %-4s block %4d: %.3f ms, %.3e attempts/s" % (layout, bt, ms, rate))
+    if not results:
+        raise ValueError("no on-chip kernel fits this torus")
+    rate, layout, bt = max(results)
+    if use_cache:
+        cache = load_cache(path)
+        cache[key] = {"layout": layout, "block_threads": bt, "attempts_per_s": rate,
+                      "candidates": [[l, b, r] for r, l, b in results]}
+        save_cache(cache, path)
+    return layout, bt
+
+
+def tuned_run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,
+                     beta1=3.0, beta_table=None, init_spins=True, cut=None, energy=None, flips=None, stream=None,
+                     path=None):
+    """run_trials with the launch shape from the tuning cache (tuned on first use)."""
+    layout, bt = tune(graph, spins.shape[0], n_sweeps=n_sweeps, schedule=schedule if schedule != "table" else
+                      "geometric", beta0=beta0 if schedule != "table" else 0.05, beta1=beta1 if schedule != "table"
+                      else 4.0, path=path)
+    run_trials(graph, spins, seed, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1, beta_table, init_spins,
+               layout, cut, energy, flips, bt, stream=stream)
+    return layout, bt
+

@@ -10,7 +10,7 @@ from tests import inputs
 pytestmark = pytest.mark.gpu
 
 SCHED = {"linear": oracle.SCHED_LINEAR, "geometric": oracle.SCHED_GEOMETRIC, "table": oracle.SCHED_TABLE}
-LAYOUTS = ["i8", "bp32"]
+LAYOUTS = ["i8", "bp32", "stream"]
 
 
 @pytest.fixture(scope="module")
@@ -213,7 +213,7 @@ def test_too_large_torus_is_rejected(dev):
     ising = _ising()
     g = ising.create_graph([256, 256], 1)
     s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
-    for layout in ("i8", "bp32", "auto"):
+    for layout in ("i8", "bp32"):  # AUTO streams it from HBM instead
         with pytest.raises(ising.IsingError) as e:
             ising.run_trials(g, s, 1, 10, layout=layout)
         assert e.value.code == ising.E_UNSUPPORTED
@@ -308,3 +308,24 @@ def test_eval_cut_empty(dev):
     s = torch.zeros((0, g.n), dtype=torch.int8, device="cuda")
     ising.eval_cut(g, s, None, None)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dims", [[1000, 1000], [64, 64, 64]])
+def test_streamed_stress_tori_sampled(dev, dims):
+    """Lattices larger than a block's LDS run from HBM (AUTO picks it); 64
+    replicas, sweeps [0, 6) of a 2,000-sweep schedule; the oracle recomputes
+    the first and last replica quads."""
+    wseed = 1000 if len(dims) == 2 else 643
+    gpu = run_gpu(dims, wseed, 77, 64, 2000, 0, 6, schedule="geometric", beta0=0.05, beta1=4.0, layout="auto")
+    for start in (0, 60):
+        orc = run_oracle(dims, wseed, 77, 4, 2000, 0, 6, "geometric", 0.05, 4.0, replica_begin=start)
+        assert_same(gpu, orc, rows=slice(start, start + 4))
+
+
+def test_streamed_matches_on_chip_layouts(dev):
+    dims = [40, 60]
+    a = run_gpu(dims, 9, 3, 70, 300, schedule="geometric", beta0=0.05, beta1=4.0, layout="stream")
+    b = run_gpu(dims, 9, 3, 70, 300, schedule="geometric", beta0=0.05, beta1=4.0, layout="bp32")
+    c = run_gpu(dims, 9, 3, 70, 300, schedule="geometric", beta0=0.05, beta1=4.0, layout="i8")
+    for x, y, z in zip(a, b, c):
+        assert (x == y).all() and (x == z).all()

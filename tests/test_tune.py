@@ -1,0 +1,48 @@
+"""Autotuner: candidate launch shapes (CPU) and tuning on the GPU, where every
+candidate must give bit-identical results."""
+import os
+
+import pytest
+
+from paper_2505_18508_amd import tune
+
+
+def test_candidates_cover_packings_and_tiles():
+    c = tune.candidates([100, 100], 1024)
+    layouts = {l for l, _ in c}
+    assert layouts == {"i8", "bp32"}
+    assert all(bt % 50 == 0 and 0 < bt <= 1024 for _, bt in c)  # multiples of Lx/2 = 50
+    # too few 32-replica groups: the bit-packed layout is not a candidate
+    assert {l for l, _ in tune.candidates([50, 100], 16)} == {"i8"}
+    assert tune.candidates([2, 4096], 64) == []  # a line wider than a block
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "t.json")
+    tune.save_cache({"a|1x2|3": {"layout": "i8", "block_threads": 50}}, path)
+    assert tune.load_cache(path)["a|1x2|3"]["block_threads"] == 50
+    assert tune.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+@pytest.mark.gpu
+def test_tuning_picks_identical_fastest_shape(tmp_path):
+    import torch
+
+    import paper_2505_18508_amd as ising
+
+    path = str(tmp_path / "tune.json")
+    g = ising.create_graph([100, 100], 2)
+    layout, bt = tune.tune(g, 1024, seed=102, n_sweeps=10000, window=50, path=path, log=print)
+    assert layout in ("i8", "bp32") and bt > 0
+    cache = tune.load_cache(path)
+    (entry,) = cache.values()
+    assert entry["layout"] == layout and len(entry["candidates"]) >= 2
+    # the cache answers the second call; the tuned launch equals the default one
+    assert tune.tune(g, 1024, path=path) == (layout, bt)
+    R = 64
+    a = torch.zeros((R, g.n), dtype=torch.int8, device="cuda")
+    b = torch.zeros((R, g.n), dtype=torch.int8, device="cuda")
+    ising.run_trials(g, a, 5, 500, schedule="geometric", beta0=0.05, beta1=4.0)
+    tune.tuned_run_trials(g, b, 5, 500, schedule="geometric", beta0=0.05, beta1=4.0, path=path)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
