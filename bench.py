@@ -37,6 +37,16 @@ WORKLOADS["c3"] = dict(
     name="batch of 2-D tori 50x100 / 100x100 / 100x140 / 100x200 (weight seeds 11-14) with 256 / 1,024 / 2,048 / "
          "4,096 replicas and 5,000 / 10,000 / 15,000 / 20,000 sweeps in one persistent launch, geometric beta "
          "0.05->4.0, run seeds 111-114")
+WORKLOADS["c5"] = dict(dims=[1000, 1000], weight_seed=1000, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
+                       beta1=4.0, name="2-D torus 1000x1000 (1,000,000 spins, weight seed 1000), 256 replicas, 2,000 "
+                                        "sweeps streamed from HBM, geometric beta 0.05->4.0, run seed 7")
+WORKLOADS["c5_3d"] = dict(dims=[64, 64, 64], weight_seed=643, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
+                          beta1=4.0, name="3-D torus 64^3 (262,144 spins, degree 6, weight seed 643), 256 replicas, "
+                                          "2,000 sweeps streamed from HBM, geometric beta 0.05->4.0, run seed 7")
+HBM_PEAK = 8e12
+# streamed layout: per sweep each 32-replica word is read and written once and
+# its neighbours' words read once: 12 bytes per word per sweep
+STREAM_BYTES_PER_WORD_SWEEP = 12
 WORKLOAD = WORKLOADS["c2"]
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU issue
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
@@ -183,8 +193,8 @@ def main():
     args = ap.parse_args()
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]
-    if args.workload == "c3":
-        args.no_cpu = True  # the oracle baseline is measured on the single-instance workloads
+    if args.workload in ("c3", "c5", "c5_3d"):
+        args.no_cpu = True  # the oracle baseline is measured on the single-instance on-chip workloads
     if args.gpus != 1:
         print("bench.py measures one GPU only: the replica-parallel path has no cross-GPU step to time "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -221,9 +231,13 @@ def main():
     stream = torch.cuda.current_stream()
     groups = (R + 31) // 32
     layout = args.layout
+    streamed = args.workload in ("c5", "c5_3d") or layout == "stream"
     if layout == "auto":
-        layout = "bp32" if groups >= torch.cuda.get_device_properties(dev).multi_processor_count else "i8"
-    kernel_name = "k_sweep_bp32" if layout == "bp32" else "k_sweep_i8"
+        if streamed:
+            layout = "stream"
+        else:
+            layout = "bp32" if groups >= torch.cuda.get_device_properties(dev).multi_processor_count else "i8"
+    kernel_name = {"bp32": "k_sweep_bp32", "i8": "k_sweep_i8", "stream": "k_halfsweep_stream"}[layout]
 
     def launch(stats=None):
         ising.run_trials(g, spins, W["seed"], S, 0, S, W["schedule"], W["beta0"], W["beta1"], None, True,
@@ -286,6 +300,11 @@ def main():
                      "draw_fraction": draws / attempts},
         "readout": {"best_cut": results[-1][0], "target": target, "P_s": p_s, "r": r, "STT_sweeps": S * r},
     }
+    if streamed:
+        # kernel_ms covers the whole launch sequence (pack, 2 S half-sweeps, unpack, cut)
+        hbm = STREAM_BYTES_PER_WORD_SWEEP * n * groups * S
+        out["hbm"] = {"algorithmic_bytes": hbm, "achieved_GBps": hbm / avg_kernel_s / 1e9,
+                      "peak_GBps": HBM_PEAK / 1e9, "frac": hbm / avg_kernel_s / HBM_PEAK}
     if cpu is not None:
         final = spins.cpu().numpy()
         cpu["parity_with_gpu"] = all(bool((final[rr] == s).all()) for rr, s in cpu_spins)

@@ -453,18 +453,23 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
     // stream-ordered working state: the words of every 32-replica group and their input flags
     const size_t wbytes = ising::stream_words_bytes(g->lat, p->n_replicas);
     const size_t groups = ((size_t)p->n_replicas + 31) / 32;
+    const size_t pbytes = ising::stream_part_bytes(g->lat, p->n_replicas, s.flips != nullptr, s.stats != nullptr);
     uint32_t* words = nullptr;
     uint32_t* bad = nullptr;
+    uint32_t* part = nullptr;
     e = hipMallocAsync((void**)&words, wbytes, st);
     if (e == hipSuccess) e = hipMallocAsync((void**)&bad, sizeof(uint32_t) * groups, st);
+    if (e == hipSuccess && pbytes) e = hipMallocAsync((void**)&part, pbytes, st);
     if (e != hipSuccess) {
       if (words) (void)hipFreeAsync(words, st);
+      if (bad) (void)hipFreeAsync(bad, st);
       if (owned) (void)hipFreeAsync(d_thr, st);
       return fail(ISING_E_NOMEM, "streamed state (%zu bytes): %s", wbytes, hipGetErrorString(e));
     }
-    e = ising::launch_sweep_stream(g, s, words, bad, st);
+    e = ising::launch_sweep_stream(g, s, words, bad, part, st);
     (void)hipFreeAsync(words, st);
     (void)hipFreeAsync(bad, st);
+    if (part) (void)hipFreeAsync(part, st);
   } else {
     e = layout == ISING_LAYOUT_BP32 ? ising::launch_sweep_bp32(g, s, st) : ising::launch_sweep_i8(g, s, st);
   }

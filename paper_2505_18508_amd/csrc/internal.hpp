@@ -57,9 +57,11 @@ hipError_t launch_sweep_i8(const ising_graph* g, const SweepLaunch& s, hipStream
 hipError_t launch_sweep_bp32(const ising_graph* g, const SweepLaunch& s, hipStream_t stream);
 // HBM-resident bit-packed sweeps; words: stream_words_bytes() of device
 // memory, bad: one uint32 per 32-replica group.
+// part: stream_part_bytes() of per-block flip and RNG counts (needed when s.flips or s.stats).
 size_t stream_words_bytes(const Lattice& L, int n_replicas);
+size_t stream_part_bytes(const Lattice& L, int n_replicas, bool flips, bool stats);
 hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint32_t* words, uint32_t* bad,
-                               hipStream_t stream);
+                               uint32_t* part, hipStream_t stream);
 hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut,
                              int64_t* energy, hipStream_t stream);
 hipError_t launch_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, hipStream_t stream);

@@ -24,8 +24,8 @@ struct StreamArgs {
   const uint8_t* wbits;  // colour-split, bit d set: weight of direction d is -1
   uint32_t* words;       // [groups][n]
   const uint32_t* thr;
-  uint32_t* flips;       // [R] or null
-  unsigned long long* stats;
+  uint32_t* part;        // [groups][blocks_x][32] block-owned flip counts, or null
+  unsigned long long* spart;  // [groups][blocks_x][2] block-owned RNG counts (STATS)
   uint64_t seed;
   int32_t n_replicas, replica_offset, groups;
 };
@@ -126,24 +126,82 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
     F = acc | (k1 & c1) | (k2 & c2) | (k3 & c3);
     if (F) w[own] = s ^ F;
   }
-  if (STATS) {  // per-wave totals: Philox blocks (8 per word) and draws
+  if (STATS) {  // block totals of Philox blocks (8 per word) and draws, kept in the block's slot
+    __shared__ uint32_t ws[kStreamBlock / 64][2];
     const uint32_t words_here = (uint32_t)__popcll(__ballot(h < (uint32_t)L.half && T1 != 0u));
     uint32_t d = n_draws;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-    if ((threadIdx.x & 63) == 0 && words_here) {
-      atomicAdd(&a.stats[0], 8ull * words_here);
-      atomicAdd(&a.stats[1], (unsigned long long)d);
+    if ((threadIdx.x & 63) == 0) {
+      ws[threadIdx.x >> 6][0] = words_here;
+      ws[threadIdx.x >> 6][1] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      unsigned long long c = 0ull;
+#pragma unroll
+      for (int k = 0; k < kStreamBlock / 64; ++k) c += ws[k][threadIdx.x];
+      if (threadIdx.x == 0) c *= 8ull;
+      a.spart[((size_t)g * gridDim.x + blockIdx.x) * 2 + threadIdx.x] += c;
     }
   }
-  // flips per replica: one ballot per replica bit, added by lane 0 of the wave
-  if (a.flips) {
-    const bool lane0 = (threadIdx.x & 63) == 0;
-    for (int j = 0; j < nvalid; ++j) {
+  // flips per replica: a ballot per replica bit gives each wave's count; the
+  // block adds its waves and keeps a running total in its own slot (the
+  // same block index owns the same slot in every launch: no atomics)
+  if (a.part) {
+    __shared__ uint32_t wc[kStreamBlock / 64][32];
+    const int wave = threadIdx.x >> 6;
+    for (int j = 0; j < 32; ++j) {
       const uint32_t c = (uint32_t)__popcll(__ballot((F >> j) & 1u));
-      if (lane0 && c) atomicAdd(&a.flips[r0 + j], c);
+      if ((threadIdx.x & 63) == 0) wc[wave][j] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+      uint32_t c = 0u;
+#pragma unroll
+      for (int k = 0; k < kStreamBlock / 64; ++k) c += wc[k][threadIdx.x];
+      uint32_t* slot = a.part + ((size_t)g * gridDim.x + blockIdx.x) * 32 + threadIdx.x;
+      *slot += c;
     }
   }
+}
+
+__global__ void k_reduce_flips(const uint32_t* part, int blocks_x, int32_t R, uint32_t* flips) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int g = r / 32, j = r % 32;
+  uint32_t c = 0u;
+  for (int b = 0; b < blocks_x; ++b) c += part[((size_t)g * blocks_x + b) * 32 + j];
+  flips[r] = c;
+}
+
+// adds the block slots of the RNG counters to the caller's two totals (one block)
+__global__ void k_reduce_stats(const unsigned long long* spart, int64_t n_slots, unsigned long long* stats) {
+  __shared__ unsigned long long red[2][256];
+  unsigned long long c0 = 0ull, c1 = 0ull;
+  for (int64_t i = threadIdx.x; i < n_slots; i += blockDim.x) {
+    c0 += spart[2 * i];
+    c1 += spart[2 * i + 1];
+  }
+  red[0][threadIdx.x] = c0;
+  red[1][threadIdx.x] = c1;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] += red[0][0];
+    stats[1] += red[1][0];
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0ull;
 }
 
 // canonical int8 [R][n] <-> words [groups][n]; bad values flagged per replica
@@ -212,19 +270,34 @@ __global__ void k_mark_invalid(const uint32_t* bad, int32_t R, int64_t* cut, int
 
 }  // namespace
 
+static int stream_blocks_x(const Lattice& L) { return (L.half + kStreamBlock - 1) / kStreamBlock; }
+
 size_t stream_words_bytes(const Lattice& L, int n_replicas) {
   return sizeof(uint32_t) * (size_t)L.n * (size_t)((n_replicas + 31) / 32);
 }
 
+size_t stream_part_bytes(const Lattice& L, int n_replicas, bool flips, bool stats) {
+  const size_t slots = (size_t)stream_blocks_x(L) * (size_t)((n_replicas + 31) / 32);
+  return (flips ? sizeof(uint32_t) * 32 * slots : 0) + (stats ? sizeof(unsigned long long) * 2 * slots : 0);
+}
+
 hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint32_t* words, uint32_t* bad,
-                               hipStream_t stream) {
+                               uint32_t* part, hipStream_t stream) {
   const Lattice& L = g->lat;
   const int groups = (s.n_replicas + 31) / 32;
+  const int bx = stream_blocks_x(L);
   const dim3 site_grid((unsigned)((L.n + 255) / 256), (unsigned)groups);
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, stream, bad, (int64_t)groups);
+  const int64_t n_slots = (int64_t)bx * groups;
+  // part: flip slots (u32 [slots][32]) first, then RNG-count slots (u64 [slots][2])
+  unsigned long long* spart =
+      s.stats ? (unsigned long long*)(part + (s.flips ? 32 * n_slots : 0)) : nullptr;
   if (s.flips)
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((s.n_replicas + 255) / 256)), dim3(256), 0, stream, s.flips,
-                       (int64_t)s.n_replicas);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((32 * n_slots + 255) / 256)), dim3(256), 0, stream, part,
+                       32 * n_slots);
+  if (s.stats)
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((2 * n_slots + 255) / 256)), dim3(256), 0, stream, spart,
+                       2 * n_slots);
   if (s.init)
     hipLaunchKernelGGL(k_init_words, site_grid, dim3(256), 0, stream, L, s.seed, s.replica_offset, words);
   else
@@ -234,13 +307,13 @@ hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint3
   a.wbits = g->d_wbits;
   a.words = words;
   a.thr = s.d_thr;
-  a.flips = s.flips;
-  a.stats = s.stats;
+  a.part = s.flips ? part : nullptr;
+  a.spart = spart;
   a.seed = s.seed;
   a.n_replicas = s.n_replicas;
   a.replica_offset = s.replica_offset;
   a.groups = groups;
-  const dim3 grid((unsigned)((L.half + kStreamBlock - 1) / kStreamBlock), (unsigned)groups);
+  const dim3 grid((unsigned)bx, (unsigned)groups);
   for (int t = s.t_begin; t < s.t_end; ++t) {
     for (int p = 0; p < 2; ++p) {
       if (g->ndim == 2) {
@@ -253,6 +326,10 @@ hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint3
     }
   }
   hipLaunchKernelGGL(k_unpack, site_grid, dim3(256), 0, stream, L, words, s.n_replicas, s.spins);
+  if (s.flips)
+    hipLaunchKernelGGL(k_reduce_flips, dim3((unsigned)((s.n_replicas + 255) / 256)), dim3(256), 0, stream, part, bx,
+                       s.n_replicas, s.flips);
+  if (s.stats) hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, stream, spart, n_slots, s.stats);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (s.cut || s.energy) {

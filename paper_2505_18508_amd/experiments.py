@@ -51,21 +51,23 @@ def first_hit_seconds(window_best, target, S, seconds):
 
 def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000, run_seeds=(201, 202, 203, 204, 205),
                    train_seeds=tuple(range(1001, 1014)), n_traj=100000, epochs=20, batch=8192, long_sweeps=200000,
-                   label="final", log=print):
+                   label="final", train_dims=None, train_replicas=None, log=print):
     import torch
 
     t_start = time.time()
-    instances = [(list(dims), ws, 5000 + ws) for ws in train_seeds]
+    train_dims = list(dims if train_dims is None else train_dims)
+    RT = R if train_replicas is None else train_replicas
+    instances = [(train_dims, ws, 5000 + ws) for ws in train_seeds]
     per_instance = len(learn.checkpoints(S, window))
-    X, Y = learn.trajectories(instances, R, S, window, label=label)
+    X, Y = learn.trajectories(instances, RT, S, window, label=label)
     # keep the first n_traj trajectories (instance-major, then replica)
     rows = []
     for k in range(len(instances)):
-        take = min(R, max(0, n_traj - k * R))
+        take = min(RT, max(0, n_traj - k * RT))
         if take == 0:
             break
         for c in range(per_instance):
-            base = (k * per_instance + c) * R
+            base = (k * per_instance + c) * RT
             rows.append(torch.arange(base, base + take, device=X.device))
     sel = torch.cat(rows)
     X, Y = X[sel].contiguous(), Y[sel].contiguous()
@@ -84,7 +86,7 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
             cuts, secs, wb = run_method(g, method, seed, R, S, window, model if method == "learned" else None, log)
             results[method].append((seed, cuts, secs, wb))
             all_best.append(int(cuts.max()))
-    long = learn.anneal(g, R, long_sweeps, 299, "geometric", 0.05, 4.0, window, "plain")
+    long = learn.anneal(g, R, max(long_sweeps, S), 299, "geometric", 0.05, 4.0, window, "plain")
     long_best = int(long["cut"].max().item())
     log("  long plain run (%d sweeps): best %d, %.1f s" % (long_sweeps, long_best, long["seconds"]))
     compared_best = max(all_best)
@@ -118,7 +120,7 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
     summary["train_loss"] = history
     summary["config"] = dict(dims=list(dims), weight_seed=weight_seed, R=R, S=S, window=window, run_seeds=list(run_seeds),
                              train_seeds=list(train_seeds), n_traj=n_traj, epochs=epochs, batch=batch,
-                             long_sweeps=long_sweeps, label=label)
+                             long_sweeps=long_sweeps, label=label, train_dims=train_dims, train_replicas=RT)
     summary["wall_seconds"] = time.time() - t_start
     g.close()
     return summary
@@ -138,13 +140,17 @@ def main(argv=None):
     ap.add_argument("--label", choices=learn.LABELS, default="final")
     ap.add_argument("--dims", default="100x200")
     ap.add_argument("--weight-seed", type=int, default=81)
+    ap.add_argument("--train-dims", default=None)
+    ap.add_argument("--train-replicas", type=int, default=None)
     args = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
     dims = tuple(int(v) for v in args.dims.split("x"))
-    s = ttt_experiment(dims=dims, weight_seed=args.weight_seed, label=args.label, R=args.replicas, S=args.sweeps, window=args.window, epochs=args.epochs,
+    tdims = None if args.train_dims is None else tuple(int(v) for v in args.train_dims.split("x"))
+    s = ttt_experiment(dims=dims, weight_seed=args.weight_seed, label=args.label, train_dims=tdims,
+                       train_replicas=args.train_replicas, R=args.replicas, S=args.sweeps, window=args.window, epochs=args.epochs,
                        train_seeds=tuple(range(1001, 1001 + args.train_instances)), n_traj=args.n_traj,
                        run_seeds=tuple(range(201, 201 + args.seeds)), long_sweeps=args.long_sweeps, log=log)
     text = json.dumps(s)
