@@ -201,7 +201,7 @@ def test_block_size_does_not_change_results(dev, bt, layout):
 
 @pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180])])
 def test_largest_on_chip_torus(dev, layout, dims):
-    # i8: 40,400 sites = 162,816 B of LDS per block; bp32: 32,400 sites = 162,448 B
+    # i8: 40,400 sites = 161,600 B of state + 272 B of tables per block; bp32: 32,400 sites = 162,448 B
     gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
     orc = run_oracle(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
