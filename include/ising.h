@@ -66,8 +66,10 @@ enum {
   ISING_LAYOUT_AUTO = 0,  /* library chooses (autotuned where a tuning exists)  */
   ISING_LAYOUT_I8 = 1,    /* 4 replicas per 32-bit word: spin + maintained field */
   ISING_LAYOUT_BP32 = 2,  /* 32 replicas per 32-bit word: one spin bit each      */
-  ISING_LAYOUT_STREAM = 3 /* 32 replicas per word, state in HBM, one launch per  */
-                          /* colour half-sweep (lattices too large for LDS)      */
+  ISING_LAYOUT_STREAM = 3, /* 32 replicas per word, state in HBM, one launch per */
+                           /* colour half-sweep (lattices too large for LDS)     */
+  ISING_LAYOUT_BS4 = 4     /* 4 replicas x 4 sites per 16-bit word, bit-sliced;  */
+                           /* needs the second-fastest axis divisible by 4       */
 };
 
 /* A cut or energy that could not be computed because the replica's spins

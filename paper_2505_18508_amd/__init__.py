@@ -19,11 +19,11 @@ LIB_PATH = os.path.join(HERE, "libising.so")
 
 OK, E_ARG, E_TOPOLOGY, E_NOMEM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 SCHED_LINEAR, SCHED_GEOMETRIC, SCHED_TABLE = 0, 1, 2
-LAYOUT_AUTO, LAYOUT_I8, LAYOUT_BP32, LAYOUT_STREAM = 0, 1, 2, 3
+LAYOUT_AUTO, LAYOUT_I8, LAYOUT_BP32, LAYOUT_STREAM, LAYOUT_BS4 = 0, 1, 2, 3, 4
 INVALID_VALUE = -(2**63)
 
 SCHEDULES = {"linear": SCHED_LINEAR, "geometric": SCHED_GEOMETRIC, "table": SCHED_TABLE}
-LAYOUTS = {"auto": LAYOUT_AUTO, "i8": LAYOUT_I8, "bp32": LAYOUT_BP32, "stream": LAYOUT_STREAM}
+LAYOUTS = {"auto": LAYOUT_AUTO, "i8": LAYOUT_I8, "bp32": LAYOUT_BP32, "stream": LAYOUT_STREAM, "bs4": LAYOUT_BS4}
 
 EXPORTED = [
     "ising_create_graph", "ising_destroy_graph", "ising_graph_info", "ising_graph_weights",

@@ -384,23 +384,34 @@ int check_run(const ising_graph* g, const ising_run_params* p, const int8_t* spi
                        ising::sweep_i8_lds_bytes(g->lat) <= dev.lds_per_block;
   const bool bp_fits = ising::sweep_bp32_block(g->lat, p->block_threads) > 0 &&
                        ising::sweep_bp32_lds_bytes(g->lat) <= dev.lds_per_block;
+  const bool bs4_fits = ising::sweep_bs4_block(g->lat, p->block_threads) > 0 &&
+                        ising::sweep_bs4_lds_bytes(g->lat) <= dev.lds_per_block;
   int layout = p->layout;
   if (layout == ISING_LAYOUT_AUTO) {
     // 32 replicas per block wins per attempt, but only fills the chip with at
-    // least one group per compute unit
+    // least one group per compute unit; below that, four replicas per block,
+    // bit-sliced over four sites where the lattice allows it
     const int64_t groups = ((int64_t)p->n_replicas + 31) / 32;
-    if (!i8_fits && !bp_fits)
-      layout = ISING_LAYOUT_STREAM;
+    if (bp_fits && (groups >= dev.cus || (!i8_fits && !bs4_fits)))
+      layout = ISING_LAYOUT_BP32;
+    else if (bs4_fits)
+      layout = ISING_LAYOUT_BS4;
+    else if (i8_fits)
+      layout = ISING_LAYOUT_I8;
     else
-      layout = (bp_fits && (groups >= dev.cus || !i8_fits)) ? ISING_LAYOUT_BP32 : ISING_LAYOUT_I8;
+      layout = ISING_LAYOUT_STREAM;
   }
   if (layout == ISING_LAYOUT_STREAM) {
     if (g->lat.hx < 1) return fail(ISING_E_UNSUPPORTED, "torus too small");
     *layout_out = layout;
     return ISING_OK;
   }
-  if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32) return fail(ISING_E_ARG, "unknown layout %d", p->layout);
-  if ((layout == ISING_LAYOUT_I8 && !i8_fits) || (layout == ISING_LAYOUT_BP32 && !bp_fits))
+  if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32 && layout != ISING_LAYOUT_BS4)
+    return fail(ISING_E_ARG, "unknown layout %d", p->layout);
+  if (layout == ISING_LAYOUT_BS4 && !ising::sweep_bs4_supported(g->lat))
+    return fail(ISING_E_UNSUPPORTED, "layout %d needs the torus' second-fastest axis divisible by 4", layout);
+  if ((layout == ISING_LAYOUT_I8 && !i8_fits) || (layout == ISING_LAYOUT_BP32 && !bp_fits) ||
+      (layout == ISING_LAYOUT_BS4 && !bs4_fits))
     return fail(ISING_E_UNSUPPORTED, "torus of %lld sites does not fit the on-chip sweep kernel of layout %d",
                 (long long)g->n, layout);
   *layout_out = layout;
@@ -471,7 +482,9 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
     (void)hipFreeAsync(bad, st);
     if (part) (void)hipFreeAsync(part, st);
   } else {
-    e = layout == ISING_LAYOUT_BP32 ? ising::launch_sweep_bp32(g, s, st) : ising::launch_sweep_i8(g, s, st);
+    e = layout == ISING_LAYOUT_BP32  ? ising::launch_sweep_bp32(g, s, st)
+        : layout == ISING_LAYOUT_BS4 ? ising::launch_sweep_bs4(g, s, st)
+                                     : ising::launch_sweep_i8(g, s, st);
   }
   if (owned) (void)hipFreeAsync(d_thr, st);
   if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");

@@ -1,0 +1,101 @@
+// Bit-sliced helpers shared by the kernels that keep one spin bit per
+// (site, replica) lane of a 32-bit word.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace ising {
+
+// Bit-sliced population count of DEG one-bit inputs per lane:
+// u = u0 + 2 u1 + 4 u2 (DEG = 4 or 6).
+template <int DEG>
+__device__ __forceinline__ void bond_count3(const uint32_t* x, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+  if (DEG == 4) {
+    const uint32_t s1 = x[0] ^ x[1], c1 = x[0] & x[1];
+    const uint32_t s2 = x[2] ^ x[3], c2 = x[2] & x[3];
+    u0 = s1 ^ s2;
+    const uint32_t k = s1 & s2;
+    u1 = xor3(c1, c2, k);
+    u2 = (c1 & c2) | (k & (c1 | c2));
+  } else {
+    const uint32_t s1 = xor3(x[0], x[1], x[2]);
+    const uint32_t c1 = (x[0] & x[1]) | (x[2] & (x[0] | x[1]));
+    const uint32_t s2 = xor3(x[3], x[4], x[5]);
+    const uint32_t c2 = (x[3] & x[4]) | (x[5] & (x[3] | x[4]));
+    u0 = s1 ^ s2;
+    const uint32_t k = s1 & s2;
+    u1 = xor3(c1, c2, k);
+    u2 = (c1 & c2) | (k & (c1 | c2));
+  }
+}
+
+// c = 2 c + (x < T): the borrow of x - T is shifted into c by one add with
+// carry, two VALU instructions per compare (T uniform).
+__device__ __forceinline__ uint32_t lt_shift_in(uint32_t c, uint32_t x, uint32_t T) {
+  uint32_t diff;
+  asm("v_subrev_co_u32_e32 %0, vcc, %2, %3\n\t"
+      "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc"
+      : "=&v"(diff), "+v"(c)
+      : "s"(T), "v"(x)
+      : "vcc");
+  return c;
+}
+
+// The four words of one Philox block shifted into LEV compare chains at once
+// (word 3 first): c_k = 16 c_k + bits (u_3 < T_k, ..., u_0 < T_k).  One asm
+// block per Philox block keeps the carry sequence free of inserted waits.
+template <int LEV>
+__device__ __forceinline__ void lt_shift_in4(uint32_t& c1, uint32_t& c2, uint32_t& c3, const uint32_t* u, uint32_t T1,
+                                             uint32_t T2, uint32_t T3) {
+  uint32_t d;
+  if (LEV == 1) {
+    asm("v_subrev_co_u32_e32 %0, vcc, %2, %3\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %2, %4\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %2, %5\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %2, %6\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc"
+        : "=&v"(d), "+v"(c1)
+        : "s"(T1), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+        : "vcc");
+  } else if (LEV == 2) {
+    asm("v_subrev_co_u32_e32 %0, vcc, %3, %5\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %4, %5\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %3, %6\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %4, %6\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %3, %7\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %4, %7\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %3, %8\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %4, %8\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc"
+        : "=&v"(d), "+v"(c1), "+v"(c2)
+        : "s"(T1), "s"(T2), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+        : "vcc");
+  } else {
+    c1 = lt_shift_in(c1, u[3], T1);
+    c2 = lt_shift_in(c2, u[3], T2);
+    c3 = lt_shift_in(c3, u[3], T3);
+    c1 = lt_shift_in(c1, u[2], T1);
+    c2 = lt_shift_in(c2, u[2], T2);
+    c3 = lt_shift_in(c3, u[2], T3);
+    c1 = lt_shift_in(c1, u[1], T1);
+    c2 = lt_shift_in(c2, u[1], T2);
+    c3 = lt_shift_in(c3, u[1], T3);
+    c1 = lt_shift_in(c1, u[0], T1);
+    c2 = lt_shift_in(c2, u[0], T2);
+    c3 = lt_shift_in(c3, u[0], T3);
+  }
+}
+
+}  // namespace ising

@@ -55,6 +55,7 @@ struct SweepLaunch {
 
 hipError_t launch_sweep_i8(const ising_graph* g, const SweepLaunch& s, hipStream_t stream);
 hipError_t launch_sweep_bp32(const ising_graph* g, const SweepLaunch& s, hipStream_t stream);
+hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStream_t stream);
 // HBM-resident bit-packed sweeps; words: stream_words_bytes() of device
 // memory, bad: one uint32 per 32-replica group.
 // part: stream_part_bytes() of per-block flip and RNG counts (needed when s.flips or s.stats).
@@ -83,8 +84,13 @@ void free_i8_batch(I8BatchPlan& plan);
 // LDS bytes one block of each sweep kernel needs for a lattice.
 size_t sweep_i8_lds_bytes(const Lattice& L);
 size_t sweep_bp32_lds_bytes(const Lattice& L);
-// Block size a sweep kernel uses for a requested size (0 = default).
+size_t sweep_bs4_lds_bytes(const Lattice& L);
+// Block size a sweep kernel uses for a requested size (0 = default; 0
+// returned when the kernel cannot take the lattice).
 int sweep_i8_block(const Lattice& L, int requested);
 int sweep_bp32_block(const Lattice& L, int requested);
+int sweep_bs4_block(const Lattice& L, int requested);
+// The 4 x 4 bit-sliced kernel needs Ly (the second-fastest axis) divisible by 4.
+bool sweep_bs4_supported(const Lattice& L);
 
 }  // namespace ising

@@ -22,6 +22,7 @@
 // cut = (W_total - H) / 2 (eq. (1)).
 #include <hip/hip_runtime.h>
 
+#include "bitslice.hpp"
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -109,12 +110,7 @@ __device__ __forceinline__ void draw_compare(uint64_t seed, uint32_t ci, uint32_
 #pragma unroll
   for (int q = 7; q >= 0; --q) {
     const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-#pragma unroll
-    for (int b = 3; b >= 0; --b) {
-      c1 = 2u * c1 + (r.v[b] < T1 ? 1u : 0u);
-      if (LEV >= 2) c2 = 2u * c2 + (r.v[b] < T2 ? 1u : 0u);
-      if (LEV >= 3) c3 = 2u * c3 + (r.v[b] < T3 ? 1u : 0u);
-    }
+    lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
   }
 }
 

@@ -11,6 +11,9 @@
 // bytes per spin-update attempt).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
+#include "bitslice.hpp"
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -108,16 +111,20 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
     if (T1 != 0u) {
       const uint32_t ci = line * (uint32_t)L.Lx + 2u * m + o;
       const uint32_t quad0 = (uint32_t)(a.replica_offset + r0) >> 2;
+      // thresholds decrease with k, so the nonzero ones are a prefix
+      auto draws = [&](auto lev) {
 #pragma unroll
-      for (int q = 7; q >= 0; --q) {
-        const u32x4 r = philox_lane_c0(a.seed, ci, (uint32_t)t, quad0 + (uint32_t)q, kTagMetropolis);
-#pragma unroll
-        for (int b = 3; b >= 0; --b) {
-          c1 = 2u * c1 + (r.v[b] < T1 ? 1u : 0u);
-          c2 = 2u * c2 + (r.v[b] < T2 ? 1u : 0u);
-          if (NDIM == 3) c3 = 2u * c3 + (r.v[b] < T3 ? 1u : 0u);
+        for (int q = 7; q >= 0; --q) {
+          const u32x4 r = philox_lane_c0(a.seed, ci, (uint32_t)t, quad0 + (uint32_t)q, kTagMetropolis);
+          lt_shift_in4<decltype(lev)::value>(c1, c2, c3, r.v, T1, T2, T3);
         }
-      }
+      };
+      if (T2 == 0u)
+        draws(std::integral_constant<int, 1>());
+      else if (NDIM == 2 || T3 == 0u)
+        draws(std::integral_constant<int, 2>());
+      else
+        draws(std::integral_constant<int, 3>());
       if (STATS) {
         const uint32_t lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
         n_draws = __popc((k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & lanes);

@@ -2,7 +2,8 @@
 
 For a (torus, replica count) the tuner times every candidate launch shape on
 a short window of the real schedule: the packing (4 replicas per block with
-maintained fields, or 32 replicas per block bit-sliced) and the tile shape
+maintained fields, 4 replicas x 4 sites bit-sliced, or 32 replicas per block
+bit-sliced) and the tile shape
 (lines of the colour-split lattice per pass, hence threads per block).
 Results never depend on the candidate -- the tuner checks that every
 candidate returns bit-identical spins, cuts, energies and flip counts --
@@ -34,10 +35,13 @@ def candidates(dims, n_replicas, cus=256):
     max_lp = min(MAX_BLOCK // hx, lines)
     lps = sorted({lp for lp in (max_lp, max_lp // 2, max_lp // 4, (max_lp // 2) * 2 if max_lp > 2 else max_lp)
                   if lp >= 1})
-    for layout in ("i8", "bp32"):
+    for layout in ("i8", "bp32", "bs4"):
         if layout == "bp32" and (n_replicas + 31) // 32 < cus // 8:
             continue  # fewer than one group per eight CUs: never competitive
-        for lp in lps:
+        if layout == "bs4" and L["Ly"] % 4:
+            continue  # four sites per word along y
+        cand_lps = lps if layout != "bs4" else sorted({max(1, min(lp, lines // 4)) for lp in lps})
+        for lp in cand_lps:
             out.append((layout, lp * hx))
     return out
 

@@ -10,7 +10,14 @@ from tests import inputs
 pytestmark = pytest.mark.gpu
 
 SCHED = {"linear": oracle.SCHED_LINEAR, "geometric": oracle.SCHED_GEOMETRIC, "table": oracle.SCHED_TABLE}
-LAYOUTS = ["i8", "bp32", "stream"]
+LAYOUTS = ["i8", "bp32", "stream", "bs4"]
+# a torus the 4 x 4 bit-sliced layout takes in place of C1 (its rows are not a multiple of 4)
+BS4_C1_DIMS = [48, 100]
+
+
+def bs4_ok(dims):
+    """The 4 x 4 bit-sliced layout needs the second-fastest axis (rows in 2-D) divisible by 4."""
+    return (dims[0] if len(dims) == 2 else dims[1]) % 4 == 0
 
 
 @pytest.fixture(scope="module")
@@ -95,9 +102,10 @@ def test_philox_stream_matches_oracle(dev):
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_c1_full_run_bit_exact(dev, layout):
     c = inputs.C1
-    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
+    dims = BS4_C1_DIMS if layout == "bs4" else c["dims"]
+    gpu = run_gpu(dims, c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
                   beta0=c["beta0"], beta1=c["beta1"], layout=layout)
-    orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
+    orc = run_oracle(dims, c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
                      beta0=c["beta0"], beta1=c["beta1"])
     assert_same(gpu, orc)
 
@@ -116,15 +124,16 @@ def test_c2_first_200_sweeps_sampled_replicas(dev, layout):
 
 
 def test_c2_layouts_agree_on_every_replica(dev):
-    """i8 and bp32 packings give identical spins, cuts, energies and flip
-    counts on all 1,024 replicas of sweeps [0, 200)."""
+    """i8, bp32 and bs4 packings give identical spins, cuts, energies and
+    flip counts on all 1,024 replicas of sweeps [0, 200)."""
     c = inputs.C2
     a = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
                 layout="i8")
-    b = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
-                layout="bp32")
-    for x, y in zip(a, b):
-        assert (x == y).all()
+    for other in ("bp32", "bs4"):
+        b = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"],
+                    c["beta1"], layout=other)
+        for x, y in zip(a, b):
+            assert (x == y).all()
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -141,9 +150,12 @@ def test_c4_shape_short_window_sampled(dev, layout):
 
 @pytest.mark.parametrize("dims,R", [([2, 2], 5), ([2, 4], 3), ([4, 2], 8), ([4, 6], 13), ([6, 8], 1), ([2, 6], 7),
                                     ([2, 2, 2], 6), ([4, 4, 6], 9), ([6, 8, 10], 4), ([2, 4, 2], 2),
-                                    ([34, 18], 11), ([10, 1000], 3), ([6, 4], 37), ([8, 6, 4], 33)])
+                                    ([34, 18], 11), ([10, 1000], 3), ([6, 4], 37), ([8, 6, 4], 33),
+                                    ([8, 6], 6), ([12, 10], 17), ([4, 1000], 5), ([2, 8, 6], 3), ([20, 34], 9)])
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_small_and_ragged_tori(dev, dims, R, layout):
+    if layout == "bs4" and not bs4_ok(dims):
+        pytest.skip("bs4 needs the second-fastest axis divisible by 4")
     gpu = run_gpu(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
     orc = run_oracle(dims, 7, 55, R, 300, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
@@ -183,7 +195,7 @@ def test_window_resume_equals_single_run(dev, layout):
 
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_replica_offset_selects_streams(dev, layout):
-    dims = [10, 12]
+    dims = [12, 10]
     full = run_gpu(dims, 3, 8, 80, 100, layout=layout)
     part = run_gpu(dims, 3, 8, 40, 100, replica_offset=12, layout=layout)
     assert (part[0] == full[0][12:52]).all()
@@ -193,15 +205,17 @@ def test_replica_offset_selects_streams(dev, layout):
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_block_size_does_not_change_results(dev, bt, layout):
     c = inputs.C1
-    ref = run_gpu(c["dims"], c["weight_seed"], c["seed"], 36, 200, schedule="linear", layout="i8")
-    got = run_gpu(c["dims"], c["weight_seed"], c["seed"], 36, 200, schedule="linear", block_threads=bt, layout=layout)
+    dims = BS4_C1_DIMS if layout == "bs4" else c["dims"]
+    ref = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", layout="i8")
+    got = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", block_threads=bt, layout=layout)
     for x, y in zip(ref, got):
         assert (x == y).all()
 
 
-@pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180])])
+@pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180]), ("bs4", [172, 172])])
 def test_largest_on_chip_torus(dev, layout, dims):
-    # i8: 40,400 sites = 161,600 B of state + 272 B of tables per block; bp32: 32,400 sites = 162,448 B
+    # i8: 40,400 sites = 161,600 B of state + 272 B of tables per block; bp32: 32,400 sites = 162,448 B;
+    # bs4: 29,584 sites = 3,698 records of 44 B = 162,712 B + 64 B
     gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
     orc = run_oracle(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
@@ -219,8 +233,21 @@ def test_too_large_torus_is_rejected(dev):
         assert e.value.code == ising.E_UNSUPPORTED
     g2 = ising.create_graph([200, 202], 1)
     s2 = torch.zeros((4, g2.n), dtype=torch.int8, device="cuda")
+    for layout in ("bp32", "bs4"):
+        with pytest.raises(ising.IsingError) as e:
+            ising.run_trials(g2, s2, 1, 10, layout=layout)
+        assert e.value.code == ising.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dims", [[50, 100], [6, 8], [4, 6, 8]])
+def test_bs4_rejects_rows_not_divisible_by_4(dev, dims):
+    import torch
+
+    ising = _ising()
+    g = ising.create_graph(dims, 1)
+    s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
     with pytest.raises(ising.IsingError) as e:
-        ising.run_trials(g2, s2, 1, 10, layout="bp32")
+        ising.run_trials(g, s, 1, 10, layout="bs4")
     assert e.value.code == ising.E_UNSUPPORTED
 
 
@@ -229,7 +256,7 @@ def test_invalid_input_spins_flagged(dev, layout):
     import torch
 
     ising = _ising()
-    g = ising.create_graph([6, 8], 2)
+    g = ising.create_graph([8, 6], 2)
     s0 = inputs.random_spins(1, 8, g.n)
     s0[3, 7] = 0
     s0[5, 0] = 3

@@ -10,10 +10,13 @@ from paper_2505_18508_amd import tune
 def test_candidates_cover_packings_and_tiles():
     c = tune.candidates([100, 100], 1024)
     layouts = {l for l, _ in c}
-    assert layouts == {"i8", "bp32"}
+    assert layouts == {"i8", "bp32", "bs4"}
     assert all(bt % 50 == 0 and 0 < bt <= 1024 for _, bt in c)  # multiples of Lx/2 = 50
-    # too few 32-replica groups: the bit-packed layout is not a candidate
+    # bs4 word lines hold 4 rows: at most 100 / 4 = 25 of them per pass
+    assert all(bt <= 25 * 50 for l, bt in c if l == "bs4")
+    # too few 32-replica groups: the bit-packed layout is not a candidate; 50 rows: no bs4
     assert {l for l, _ in tune.candidates([50, 100], 16)} == {"i8"}
+    assert {l for l, _ in tune.candidates([48, 100], 16)} == {"i8", "bs4"}
     assert tune.candidates([2, 4096], 64) == []  # a line wider than a block
 
 
@@ -33,7 +36,7 @@ def test_tuning_picks_identical_fastest_shape(tmp_path):
     path = str(tmp_path / "tune.json")
     g = ising.create_graph([100, 100], 2)
     layout, bt = tune.tune(g, 1024, seed=102, n_sweeps=10000, window=50, path=path, log=print)
-    assert layout in ("i8", "bp32") and bt > 0
+    assert layout in ("i8", "bp32", "bs4") and bt > 0
     cache = tune.load_cache(path)
     (entry,) = cache.values()
     assert entry["layout"] == layout and len(entry["candidates"]) >= 2
