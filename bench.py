@@ -4,9 +4,11 @@ Metropolis annealing on one MI355X.
 Workload (default): 2-D toroidal grid 100 x 100 (10,000 spins, 20,000 +/-1
 edges from weight seed 2), 1,024 replicas, 10,000 sweeps, geometric beta
 0.05 -> 4.0, run seed 102.  One step = one whole pass of the hot path over
-that batch: Philox initial state, the full sweep schedule with maintained
-fields and flip counters, exact cut/energy, and the host readout (best cut,
-success probability, repetitions r of eq. (3), sweeps-to-target of eq. (4)).
+that batch: Philox initial state, the full sweep schedule with flip counters,
+exact cut/energy, and the host readout (best cut, success probability,
+repetitions r of eq. (3), sweeps-to-target of eq. (4)).  The library picks
+the packing (for this replica count: 4 replicas x 4 sites bit-sliced per
+LDS word); --layout forces another.
 
 Prints one JSON line.  Inputs are synthetic (the paper's Gset instances are
 not available); the instance is generated from its seed on the host.
@@ -230,14 +232,10 @@ def main():
     flips = torch.zeros(R, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     groups = (R + 31) // 32
-    layout = args.layout
-    streamed = args.workload in ("c5", "c5_3d") or layout == "stream"
-    if layout == "auto":
-        if streamed:
-            layout = "stream"
-        else:
-            layout = "bp32" if groups >= torch.cuda.get_device_properties(dev).multi_processor_count else "i8"
-    kernel_name = {"bp32": "k_sweep_bp32", "i8": "k_sweep_i8", "stream": "k_halfsweep_stream"}[layout]
+    layout = ising.select_layout(g, R, S, args.layout, args.block_threads)  # the packing the library runs
+    streamed = layout == "stream"
+    kernel_name = {"bp32": "k_sweep_bp32", "i8": "k_sweep_i8", "stream": "k_halfsweep_stream",
+                   "bs4": "k_sweep_bs4"}[layout]
 
     def launch(stats=None):
         ising.run_trials(g, spins, W["seed"], S, 0, S, W["schedule"], W["beta0"], W["beta1"], None, True,
@@ -290,7 +288,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": W["name"], "layout": args.layout, "replicas": R, "sweeps": S, "spins": n},
+        "config": {"workload": W["name"], "layout": layout, "replicas": R, "sweeps": S, "spins": n},
         "kernel_attempts_per_s": attempts / avg_kernel_s,
         "kernel_ms": avg_kernel_s * 1e3,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,

@@ -133,8 +133,7 @@ typedef struct {
   int32_t block_threads;     /* 0: library default / tuned; else threads per block   */
                              /* (rounded to the kernel's granularity)                */
   int32_t replica_offset;    /* global id of replica 0 of this call (Philox streams */
-                             /* are keyed by global ids); multiple of 4 (i8) or 32   */
-                             /* (bp32); normally 0                                   */
+                             /* are keyed by global ids); a multiple of 4; normally 0 */
   uint64_t* stats_out;       /* device uint64[2] or NULL: the run adds the number of */
                              /* Philox4x32-10 blocks it evaluated to [0] and the     */
                              /* number of attempts that needed a uniform (dE > 0 and */
@@ -160,6 +159,13 @@ typedef struct {
  */
 int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout,
                      int64_t* cut_out, int64_t* energy_out, uint32_t* flips_out, void* stream);
+
+/*
+ * The ISING_LAYOUT_* that ising_run_trials would use for g and p (p->layout
+ * AUTO resolved), into *layout_out.  Validates g and p as ising_run_trials
+ * does (same error codes) and launches nothing; no spins buffer is needed.
+ */
+int ising_select_layout(const ising_graph* g, const ising_run_params* p, int32_t* layout_out);
 
 /*
  * Exact cut (eq. (1)) and energy (eq. (2), J = -w, h = 0) of R states.

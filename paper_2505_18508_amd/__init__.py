@@ -27,7 +27,7 @@ LAYOUTS = {"auto": LAYOUT_AUTO, "i8": LAYOUT_I8, "bp32": LAYOUT_BP32, "stream": 
 
 EXPORTED = [
     "ising_create_graph", "ising_destroy_graph", "ising_graph_info", "ising_graph_weights",
-    "ising_generate_weights", "ising_run_trials", "ising_eval_cut", "ising_thresholds",
+    "ising_generate_weights", "ising_run_trials", "ising_select_layout", "ising_eval_cut", "ising_thresholds",
     "ising_philox_dump", "ising_last_error",
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
@@ -214,6 +214,14 @@ def make_params(seed, n_replicas, n_sweeps, sweep_begin=0, sweep_end=None, sched
     p.replica_offset = int(replica_offset)
     p.stats_out = None if stats is None else _ptr(stats).value
     return p, keep
+
+
+def select_layout(graph, n_replicas, n_sweeps=1, layout="auto", block_threads=0):
+    """Name of the packing ising_run_trials would use for R replicas (AUTO resolved)."""
+    p, _ = make_params(0, n_replicas, n_sweeps, layout=layout, block_threads=block_threads)
+    out = ctypes.c_int32(0)
+    _check(lib().ising_select_layout(graph.handle, ctypes.byref(p), ctypes.byref(out)))
+    return {v: k for k, v in LAYOUTS.items()}[out.value]
 
 
 def run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,

@@ -448,6 +448,16 @@ struct ising_batch {
 
 extern "C" {
 
+int ising_select_layout(const ising_graph* g, const ising_run_params* p, int32_t* layout_out) {
+  if (!layout_out) return fail(ISING_E_ARG, "layout_out is NULL");
+  int8_t placeholder = 0;  // validation only: no spins are read
+  int layout = 0;
+  const int rc = check_run(g, p, &placeholder, &layout);
+  if (rc) return rc;
+  *layout_out = layout;
+  return ISING_OK;
+}
+
 int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout, int64_t* cut_out,
                      int64_t* energy_out, uint32_t* flips_out, void* stream) {
   int layout = 0;

@@ -356,3 +356,14 @@ def test_streamed_matches_on_chip_layouts(dev):
     c = run_gpu(dims, 9, 3, 70, 300, schedule="geometric", beta0=0.05, beta1=4.0, layout="i8")
     for x, y, z in zip(a, b, c):
         assert (x == y).all() and (x == z).all()
+
+
+@pytest.mark.parametrize("dims,R,want", [([100, 100], 1024, "bs4"), ([100, 200], 8192, "bp32"), ([50, 100], 16, "i8"),
+                                         ([1000, 1000], 256, "stream"), ([200, 202], 4, "i8"),
+                                         ([64, 64, 64], 256, "stream"), ([16, 16, 16], 40, "bs4")])
+def test_select_layout_reports_the_auto_choice(dev, dims, R, want):
+    ising = _ising()
+    g = ising.create_graph(dims, 1)
+    assert ising.select_layout(g, R) == want
+    assert ising.select_layout(g, R, layout="stream") == "stream"
+    g.close()
