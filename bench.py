@@ -71,8 +71,10 @@ def measured_traffic(kernel, workload):
     rec = json.load(open(path)).get("%s/%s" % (kernel, workload))
     if rec is None:
         return None
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    h = hashlib.sha256()
+    for f in rec["sources"]:  # the kernel's source file and every header it includes
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["sources_sha256"]:
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
 
