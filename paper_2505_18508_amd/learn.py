@@ -2,9 +2,10 @@
 
 A trial (paper, Section III) is a run of S sweeps read out at its end.  Here
 R trials run together and, every `window` sweeps, each replica's trajectory
-features go through a small network that predicts the cut the replica will
-still gain by the end of its trial; current cut plus predicted gain ranks the
-replicas, and the lower half is replaced by copies of the upper half.  Every
+features go through a small network that predicts its end-of-trial cut
+(label "final"), or the cut it will still gain (label "gain", scored as
+current cut plus predicted gain); the score ranks the replicas, and the
+lower half is replaced by copies of the upper half.  Every
 replica keeps its own Philox stream, so copies diverge at once.  The plain
 form (no culling) runs the same windows and is what the learned form is
 judged against, with eq. (3)-(5) applied to both.
