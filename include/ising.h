@@ -172,7 +172,10 @@ int ising_select_layout(const ising_graph* g, const ising_run_params* p, int32_t
  *   spins        device int8 [n_replicas][n], canonical layout.
  *   cut_out, energy_out  device int64 [n_replicas]; either may be NULL.
  *   A replica holding a value other than +1 / -1 gets ISING_INVALID_VALUE.
- * Asynchronous on `stream`.
+ * Asynchronous on `stream`.  Lattices above 65,536 sites split each replica
+ * into chunks whose sums pass through 24 bytes of stream-ordered scratch per
+ * chunk and replica (allocated and freed on `stream`; ISING_E_NOMEM if that
+ * fails).
  */
 int ising_eval_cut(const ising_graph* g, const int8_t* spins, int64_t n_replicas,
                    int64_t* cut_out, int64_t* energy_out, void* stream);

@@ -580,6 +580,7 @@ int ising_eval_cut(const ising_graph* g, const int8_t* spins, int64_t n_replicas
   int rc = check_device(g);
   if (rc) return rc;
   hipError_t e = ising::launch_cut_energy(g, spins, n_replicas, cut_out, energy_out, (hipStream_t)stream);
+  if (e == hipErrorOutOfMemory) return fail(ISING_E_NOMEM, "cut scratch: %s", hipGetErrorString(e));
   if (e != hipSuccess) return fail_hip(e, "cut kernel launch");
   return ISING_OK;
 }

@@ -1,7 +1,8 @@
 // Exact cut and energy of R states (paper, Section II): for every edge e =
 // (a, b), counted once, cut += w_e [s_a != s_b] (eq. (1)) and
-// H += w_e s_a s_b (eq. (2) with J = -w, h = 0).  One block per replica,
-// integer arithmetic throughout.
+// H += w_e s_a s_b (eq. (2) with J = -w, h = 0).  One block per replica, or
+// per 65,536-site chunk of a replica on large lattices; integer arithmetic
+// throughout.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -12,22 +13,30 @@ namespace ising {
 namespace {
 
 constexpr int kCutBlock = 256;
+constexpr uint32_t kCutChunk = 65536;  // sites per block on large lattices
 
+// Sums of one chunk [i0, i1) of one replica: cut, energy and the count of
+// values other than +1 / -1.  part == nullptr: the chunk is the whole
+// replica and the block writes the outputs itself.
 template <int NDIM>
 __global__ void __launch_bounds__(kCutBlock) k_cut_energy(Lattice L, const int8_t* w, const int8_t* spins,
+                                                          uint32_t chunk, uint32_t n_chunks, int64_t* part,
                                                           int64_t* cut, int64_t* energy) {
   const size_t n = (size_t)L.n;
-  const int8_t* s = spins + (size_t)blockIdx.x * n;
+  const uint32_t r = blockIdx.x / n_chunks, ch = blockIdx.x - r * n_chunks;
+  const int8_t* s = spins + (size_t)r * n;
   const uint32_t Lx = (uint32_t)L.Lx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz;
   const uint32_t plane = Lx * Ly;
+  const uint32_t i0 = ch * chunk;
+  const uint32_t i1 = min((uint32_t)L.n, i0 + chunk);
   int32_t c = 0, h = 0, bad = 0;
-  for (uint32_t i = threadIdx.x; i < (uint32_t)L.n; i += kCutBlock) {
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += kCutBlock) {
     const uint32_t line = fdiv(i, L.div_lx);
     const uint32_t x = i - line * Lx;
     const uint32_t z = NDIM == 2 ? 0u : fdiv(line, L.div_ly);
     const uint32_t y = line - z * Ly;
     const int si = s[i];
-    bad |= (si != 1 && si != -1);
+    bad += (si != 1 && si != -1) ? 1 : 0;
     uint32_t nb[NDIM];
     nb[0] = (x + 1u == Lx) ? i + 1u - Lx : i + 1u;
     nb[1] = (y + 1u == Ly) ? i + Lx - plane : i + Lx;
@@ -44,9 +53,33 @@ __global__ void __launch_bounds__(kCutBlock) k_cut_energy(Lattice L, const int8_
   const int64_t ht = block_sum<kCutBlock>((int64_t)h);
   const int64_t bt = block_sum<kCutBlock>((int64_t)bad);
   if (threadIdx.x == 0) {
-    if (cut) cut[blockIdx.x] = bt ? INT64_MIN : ct;
-    if (energy) energy[blockIdx.x] = bt ? INT64_MIN : ht;
+    if (part) {
+      int64_t* q = part + 3 * (size_t)blockIdx.x;
+      q[0] = ct;
+      q[1] = ht;
+      q[2] = bt;
+    } else {
+      if (cut) cut[r] = bt ? INT64_MIN : ct;
+      if (energy) energy[r] = bt ? INT64_MIN : ht;
+    }
   }
+}
+
+// Per replica, the chunk sums in chunk order (exact integers: the result
+// does not depend on how the lattice was split).
+__global__ void k_cut_finish(const int64_t* part, uint32_t n_chunks, int64_t n_replicas, int64_t* cut,
+                             int64_t* energy) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_replicas) return;
+  int64_t c = 0, h = 0, b = 0;
+  for (uint32_t k = 0; k < n_chunks; ++k) {
+    const int64_t* q = part + 3 * ((size_t)r * n_chunks + k);
+    c += q[0];
+    h += q[1];
+    b += q[2];
+  }
+  if (cut) cut[r] = b ? INT64_MIN : c;
+  if (energy) energy[r] = b ? INT64_MIN : h;
 }
 
 __global__ void k_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out) {
@@ -64,13 +97,30 @@ __global__ void k_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint
 
 hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut,
                              int64_t* energy, hipStream_t stream) {
-  if (n_replicas == 0) return hipSuccess;
+  if (n_replicas == 0 || (!cut && !energy)) return hipSuccess;
+  // large lattices: several blocks per replica, so that enough loads are in
+  // flight; their sums go through a stream-ordered scratch array
+  const uint32_t n = (uint32_t)g->lat.n;
+  const uint32_t n_chunks = (n + kCutChunk - 1) / kCutChunk;
+  const uint32_t chunk = n_chunks == 1 ? n : kCutChunk;
+  if ((int64_t)n_chunks * n_replicas > INT32_MAX) return hipErrorInvalidValue;
+  int64_t* part = nullptr;
+  if (n_chunks > 1) {
+    hipError_t e = hipMallocAsync((void**)&part, sizeof(int64_t) * 3 * (size_t)n_chunks * (size_t)n_replicas, stream);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((unsigned)(n_chunks * n_replicas));
   if (g->ndim == 2)
-    hipLaunchKernelGGL(k_cut_energy<2>, dim3((unsigned)n_replicas), dim3(kCutBlock), 0, stream, g->lat, g->d_w,
-                       spins, cut, energy);
+    hipLaunchKernelGGL(k_cut_energy<2>, grid, dim3(kCutBlock), 0, stream, g->lat, g->d_w, spins, chunk, n_chunks,
+                       part, cut, energy);
   else
-    hipLaunchKernelGGL(k_cut_energy<3>, dim3((unsigned)n_replicas), dim3(kCutBlock), 0, stream, g->lat, g->d_w,
-                       spins, cut, energy);
+    hipLaunchKernelGGL(k_cut_energy<3>, grid, dim3(kCutBlock), 0, stream, g->lat, g->d_w, spins, chunk, n_chunks,
+                       part, cut, energy);
+  if (part) {
+    hipLaunchKernelGGL(k_cut_finish, dim3((unsigned)((n_replicas + 255) / 256)), dim3(256), 0, stream, part, n_chunks,
+                       n_replicas, cut, energy);
+    (void)hipFreeAsync(part, stream);
+  }
   return hipGetLastError();
 }
 
