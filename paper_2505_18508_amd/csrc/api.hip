@@ -440,7 +440,7 @@ ising::SweepLaunch make_launch(const ising_run_params* p, const uint32_t* d_thr,
 }  // namespace
 
 struct ising_batch {
-  ising::I8BatchPlan plan;
+  ising::BatchPlan plan;
   std::vector<uint32_t*> owned_tables;
   int64_t attempts = 0;
   int device = 0;
@@ -510,6 +510,7 @@ int ising_batch_create(int32_t n_inst, const ising_graph* const* graphs, const i
   ising_batch* b = new (std::nothrow) ising_batch();
   if (!b) return fail(ISING_E_NOMEM, "batch handle");
   std::vector<ising::SweepLaunch> launches((size_t)n_inst);
+  std::vector<int> layouts((size_t)n_inst);
   auto bail = [&](int code) {
     for (uint32_t* t : b->owned_tables) (void)hipFree(t);
     delete b;
@@ -522,10 +523,15 @@ int ising_batch_create(int32_t n_inst, const ising_graph* const* graphs, const i
     int rc = check_run(g, p, spins[k], &layout);
     if (rc) return bail(rc);
     if (g->ndim != graphs[0]->ndim) return bail(fail(ISING_E_ARG, "instances of a batch must share ndim"));
-    if (p->layout != ISING_LAYOUT_AUTO && p->layout != ISING_LAYOUT_I8)
-      return bail(fail(ISING_E_UNSUPPORTED, "batches use the four-replica layout"));
-    if (ising::sweep_i8_lds_bytes(g->lat) > device_info(g->device).lds_per_block || ising::sweep_i8_block(g->lat, 0) <= 0)
-      return bail(fail(ISING_E_UNSUPPORTED, "instance %d does not fit the four-replica kernel", k));
+    if (p->layout != ISING_LAYOUT_AUTO && p->layout != ISING_LAYOUT_I8 && p->layout != ISING_LAYOUT_BS4)
+      return bail(fail(ISING_E_UNSUPPORTED, "batches use the four-replica layouts (i8, bs4)"));
+    const size_t lds_max = device_info(g->device).lds_per_block;
+    const bool bs4_ok = ising::sweep_bs4_block(g->lat, 0) > 0 && ising::sweep_bs4_lds_bytes(g->lat) <= lds_max;
+    const bool i8_ok = ising::sweep_i8_block(g->lat, 0) > 0 && ising::sweep_i8_lds_bytes(g->lat) <= lds_max;
+    int lay = p->layout == ISING_LAYOUT_AUTO ? (bs4_ok ? ISING_LAYOUT_BS4 : ISING_LAYOUT_I8) : p->layout;
+    if ((lay == ISING_LAYOUT_BS4 && !bs4_ok) || (lay == ISING_LAYOUT_I8 && !i8_ok))
+      return bail(fail(ISING_E_UNSUPPORTED, "instance %d does not fit the four-replica kernel of layout %d", k, lay));
+    layouts[(size_t)k] = lay;
     if (p->stats_out) return bail(fail(ISING_E_UNSUPPORTED, "batches do not collect RNG statistics"));
     uint32_t* d_thr = nullptr;
     bool owned = false;
@@ -537,9 +543,9 @@ int ising_batch_create(int32_t n_inst, const ising_graph* const* graphs, const i
     b->attempts += (int64_t)p->n_replicas * g->n * (p->sweep_end - p->sweep_begin);
   }
   b->device = graphs[0]->device;
-  hipError_t e = ising::build_i8_batch(graphs, launches.data(), n_inst, &b->plan);
+  hipError_t e = ising::build_batch(graphs, launches.data(), layouts.data(), n_inst, &b->plan);
   if (e != hipSuccess) {
-    ising::free_i8_batch(b->plan);
+    ising::free_batch(b->plan);
     return bail(fail_hip(e, "batch plan"));
   }
   *out = b;
@@ -552,7 +558,7 @@ int ising_batch_run(ising_batch* b, void* stream) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
   if (dev != b->device) return fail(ISING_E_STATE, "batch lives on device %d but device %d is current", b->device, dev);
-  e = ising::run_i8_batch(b->plan, (hipStream_t)stream);
+  e = ising::run_batch(b->plan, (hipStream_t)stream);
   return e == hipSuccess ? ISING_OK : fail_hip(e, "batch launch");
 }
 
@@ -567,7 +573,7 @@ int ising_batch_info(const ising_batch* b, int64_t* n_items, int64_t* attempts, 
 
 void ising_batch_destroy(ising_batch* b) {
   if (!b) return;
-  ising::free_i8_batch(b->plan);
+  ising::free_batch(b->plan);
   for (uint32_t* t : b->owned_tables) (void)hipFree(t);
   delete b;
 }

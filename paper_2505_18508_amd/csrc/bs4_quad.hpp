@@ -1,0 +1,355 @@
+// Checkerboard Metropolis sweeps, bit-sliced over 4 replicas x 4 sites per
+// 16-bit LDS word.
+//
+// For replica counts too small to fill the chip with 32-replica groups, a
+// block owns one replica quad (4q .. 4q+3), as the byte-per-replica kernel
+// does, but keeps only spin bits on chip and packs four sites of one colour
+// with each replica quad into one 16-bit word, so that the bond logic of a
+// visit serves 16 (site, replica) attempts at once.
+//
+// Word g = gl * hx + m of colour p holds the colour-p sites at column m
+// (x = 2m + o) of the lines 4 gl .. 4 gl + 3 (line = z Ly + y; the lines of
+// a word share z because Ly is a multiple of 4); bit 4 j + r is the spin
+// (1: +1) of replica 4q + r at line 4 gl + j.  LDS holds one record of
+// 32-bit entries per g: the colour-0 and colour-1 words, then per colour one
+// weight mask per direction slot (nibble j all ones iff that bond of site j
+// has weight +1); the record stride is odd, so a wave's records fall in
+// distinct banks.  The neighbours of lane (j, r), all in the other colour:
+//   x-same   word g, same lane (the x neighbour stored under column m)
+//   x-shift  column m + 1 where o = 1, m - 1 where o = 0; o alternates with
+//            j, so the two column words are merged by a nibble mask
+//   +y, -y   word g shifted by one nibble, the nibble shifted in taken from
+//            the next / previous word of the same plane (torus wrap in y)
+//   +z, -z   word g of the next / previous plane
+// A visit finds the unsatisfied bonds (w s_i s_j = +1) of all 16 lanes with
+// one three-way xor per slot, counts them bit-sliced (u = 0..deg) and flips
+// lanes with u >= deg/2 (dE <= 0) and lanes with dE = 4k > 0 whose Philox
+// word of (site, sweep, quad, tag 0) for that replica is below T_k(sweep)
+// (Section III's sweep: colour 0, then colour 1; same-colour sites are never
+// neighbours on an even torus, so the result is the sequential sweep's bit
+// for bit).
+//
+// After the window: spins written back in canonical layout, accepted flips
+// per replica, and the energy H = sum over colour-0 sites of s_i f_i =
+// 2 (unsatisfied bonds at colour-0 sites) - |E| (eq. (2), J = -w, h = 0),
+// cut = (W_total - H) / 2 (eq. (1)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bitslice.hpp"
+#include "lattice.hpp"
+#include "philox.hpp"
+
+namespace ising {
+namespace bs4q {
+
+constexpr int kMaxBlock = 1024;
+constexpr int kExtraWords = 16;  // [0,4) flips, 4 invalid flags, [8,12) unsatisfied bonds at colour 0
+
+// 32-bit entries per record: 2 spin words + 2 colours x deg weight masks,
+// padded to an odd count
+template <int NDIM>
+constexpr int rec_words() {
+  return NDIM == 2 ? 11 : 15;
+}
+
+struct Bs4Args {
+  Lattice lat;
+  const uint8_t* wbits;  // colour-split order, bit d set: weight of direction d (+x,-x,+y,-y,+z,-z) is -1
+  int8_t* spins;
+  const uint32_t* thr;
+  int64_t* cut;
+  int64_t* energy;
+  uint32_t* flips;
+  unsigned long long* stats;
+  uint64_t seed;
+  int64_t w_total;
+  int32_t n_replicas;
+  int32_t replica_offset;
+  int32_t t_begin, t_end;
+  int32_t init;
+  int32_t lp;  // word lines per pass: block = hx * lp
+};
+
+// What one thread needs to walk its words: fixed column m, word lines
+// gl0, gl0 + lp, ...; byte offsets between records.
+struct Bs4Walk {
+  uint32_t base0;          // record of (gl0, m)
+  uint32_t du, dd;         // record of column m + 1 / m - 1, relative
+  uint32_t step;           // records of lp word lines
+  uint32_t row, plane;     // records of one word line / one plane
+  uint32_t Y0, z0, lp_y, lp_z, LY4, Lz;
+  uint32_t ci0, ci_step;   // canonical index of (line 4 gl0, x = 2m), per pass
+  uint32_t GL, gl0, lp;
+};
+
+// Unsatisfied bonds of the 16 lanes of colour-P word at record `base`,
+// counted bit-sliced: u = u0 + 2 u1 + 4 u2.
+template <int NDIM, int P>
+__device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const Bs4Walk& wk, uint32_t Y, uint32_t z,
+                                          uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+  constexpr int DEG = 2 * NDIM;
+  constexpr int O = 1 - P;
+  const uint32_t* rec = (const uint32_t*)(lds + base);
+  own = rec[P];
+  const uint32_t xs = rec[O];
+  const uint32_t xu = ((const uint32_t*)(lds + base + wk.du))[O];
+  const uint32_t xd = ((const uint32_t*)(lds + base + wk.dd))[O];
+  const uint32_t yp = (Y + 1u == wk.LY4) ? base + wk.row - wk.plane : base + wk.row;
+  const uint32_t ym = (Y == 0u) ? base + wk.plane - wk.row : base - wk.row;
+  const uint32_t yn = ((const uint32_t*)(lds + yp))[O];
+  const uint32_t yv = ((const uint32_t*)(lds + ym))[O];
+  const uint32_t q = ((uint32_t)P + z) & 1u;      // o of the word's first site
+  const uint32_t sel = q ? 0x0F0Fu : 0xF0F0u;     // nibbles whose x-shift neighbour is at m + 1
+  uint32_t nb[DEG];
+  nb[0] = xs;
+  nb[1] = (xu & sel) | (xd & ~sel);
+  nb[2] = (xs >> 4) | (yn << 12);
+  nb[3] = (xs << 4) | (yv >> 12);
+  if (NDIM == 3) {
+    const uint32_t vol = wk.plane * wk.Lz;
+    const uint32_t zp = (z + 1u == wk.Lz) ? base + wk.plane - vol : base + wk.plane;
+    const uint32_t zm = (z == 0u) ? base + vol - wk.plane : base - wk.plane;
+    nb[DEG - 2] = ((const uint32_t*)(lds + zp))[O];
+    nb[DEG - 1] = ((const uint32_t*)(lds + zm))[O];
+  }
+  uint32_t x[DEG];
+#pragma unroll
+  for (int d = 0; d < DEG; ++d) x[d] = xor3(own, nb[d], rec[2 + P * DEG + d]);
+  bond_count3<DEG>(x, u0, u1, u2);
+}
+
+// The draws of a word's four sites and their compares against the first LEV
+// thresholds: bit 4 j + r of c_k = (Philox word r of site j) < T_k.  Site
+// j's canonical index: line 4 gl + j, x = 2m + (q ^ (j & 1)).
+template <int LEV>
+__device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t Lx, uint32_t q, uint32_t t,
+                                          uint32_t quad, uint32_t T1, uint32_t T2, uint32_t T3, uint32_t& c1,
+                                          uint32_t& c2, uint32_t& c3) {
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+    const uint32_t ci = ci0 + (uint32_t)j * Lx + (q ^ (uint32_t)(j & 1));
+    const u32x4 r = philox_lane_c0(seed, ci, t, quad, kTagMetropolis);
+    lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
+  }
+}
+
+// One half-sweep of colour P over this thread's words.
+template <int NDIM, int P, bool FLIPS, bool STATS>
+__device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4Args& a, int t, uint32_t quad,
+                                         uint32_t T1, uint32_t T2, uint32_t T3, uint32_t valid16, uint32_t* fl,
+                                         uint32_t& n_blocks, uint32_t& n_draws) {
+  const uint32_t Lx = (uint32_t)a.lat.Lx;
+  uint32_t base = wk.base0, ci0 = wk.ci0;
+  uint32_t Y = wk.Y0, z = wk.z0;
+  for (uint32_t gl = wk.gl0; gl < wk.GL; gl += wk.lp) {
+    uint32_t s, u0, u1, u2;
+    bs4_bonds<NDIM, P>(lds, base, wk, Y, z, s, u0, u1, u2);
+    // dE = 2 deg - 4u: flip when u >= deg/2; else k = deg/2 - u
+    uint32_t acc, k1, k2, k3 = 0u;
+    if (NDIM == 2) {
+      acc = u1 | u2;
+      k1 = u0 & ~acc;
+      k2 = ~(u0 | acc);
+    } else {
+      acc = u2 | (u1 & u0);
+      k1 = u1 & ~u0 & ~u2;
+      k2 = u0 & ~u1 & ~u2;
+      k3 = ~(u0 | u1 | u2);
+    }
+    uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
+    if (T1 != 0u) {
+      const uint32_t q = ((uint32_t)P + z) & 1u;
+      // thresholds decrease with k, so the nonzero ones are a prefix
+      if (T2 == 0u)
+        bs4_draws<1>(a.seed, ci0, Lx, q, (uint32_t)t, quad, T1, T2, T3, c1, c2, c3);
+      else if (NDIM == 2 || T3 == 0u)
+        bs4_draws<2>(a.seed, ci0, Lx, q, (uint32_t)t, quad, T1, T2, T3, c1, c2, c3);
+      else
+        bs4_draws<3>(a.seed, ci0, Lx, q, (uint32_t)t, quad, T1, T2, T3, c1, c2, c3);
+      if (STATS) {
+        const uint32_t need = (k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & valid16;
+        n_blocks += 4u;
+        n_draws += __popc(need);
+      }
+    }
+    const uint32_t F = (acc | (k1 & c1) | (k2 & c2) | (k3 & c3)) & 0xFFFFu;
+    if (F) ((uint32_t*)(lds + base))[P] = s ^ F;
+    if (FLIPS) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fl[b] += __popc(F & (0x1111u << b));
+    }
+    base += wk.step;
+    ci0 += wk.ci_step;
+    Y += wk.lp_y;
+    z += wk.lp_z;
+    if (Y >= wk.LY4) {
+      Y -= wk.LY4;
+      z += 1u;
+    }
+  }
+}
+
+// One replica quad (local replicas r0 .. r0+3) for the window of a.  Called
+// by every thread of a block; lds holds sweep_bs4_lds_bytes(a.lat) - 64
+// bytes of records and extra kExtraWords words.
+template <int NDIM, bool FLIPS, bool STATS>
+__device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_t* lds, uint32_t* extra) {
+  constexpr int DEG = 2 * NDIM;
+  constexpr uint32_t RS = (uint32_t)rec_words<NDIM>();
+  const Lattice& L = a.lat;
+  const uint32_t hx = (uint32_t)L.hx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz, Lx = (uint32_t)L.Lx;
+  const uint32_t LY4 = Ly / 4u;                // word lines per plane
+  const uint32_t GL = (uint32_t)L.lines / 4u;  // word lines
+  const uint32_t G = GL * hx;                  // records
+  const int tid = threadIdx.x;
+  const int B = blockDim.x;
+  const int nvalid = min(4, a.n_replicas - r0);
+  const uint32_t quad = (uint32_t)(a.replica_offset + r0) >> 2;
+  const size_t n = (size_t)L.n;
+
+  for (int k = tid; k < kExtraWords; k += B) extra[k] = 0u;
+
+  // ---- state and weight masks in, one (colour, word) per step ----------------
+  uint32_t bad = 0u;
+  for (uint32_t u = tid; u < 2u * G; u += B) {
+    const uint32_t p = u >= G ? 1u : 0u;
+    const uint32_t g = u - p * G;
+    const uint32_t gl = g / hx, m = g - gl * hx;
+    const uint32_t z = gl / LY4;
+    uint32_t word = 0u;
+    uint32_t wm[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) wm[d] = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t line = 4u * gl + (uint32_t)j;
+      const uint32_t y = line - z * Ly;
+      const uint32_t o = (p + y + z) & 1u;
+      const uint32_t ci = line * Lx + 2u * m + o;
+      const uint32_t wb = a.wbits[p * (uint32_t)L.half + line * hx + m];
+      // direction order -> slot order: x-same is +x when o = 0, -x when o = 1
+      const uint32_t ws = o ? ((wb & ~3u) | ((wb & 1u) << 1) | ((wb >> 1) & 1u)) : wb;
+#pragma unroll
+      for (int d = 0; d < DEG; ++d)
+        if (!((ws >> d) & 1u)) wm[d] |= 0xFu << (4 * j);
+      if (a.init) {
+        const u32x4 r = philox_lane_c0(a.seed, ci, 0u, quad, kTagInit);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word |= (r.v[b] >> 31) << (4 * j + b);
+      } else {
+        for (int b = 0; b < nvalid; ++b) {
+          const int8_t v = a.spins[(size_t)(r0 + b) * n + ci];
+          word |= (v > 0 ? 1u : 0u) << (4 * j + b);
+          bad |= (v != 1 && v != -1) ? (1u << b) : 0u;
+        }
+      }
+    }
+    uint32_t* rec = lds + g * RS;
+    rec[p] = word;
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) rec[2u + p * DEG + (uint32_t)d] = wm[d];
+    if (p == 0u) rec[RS - 1u] = 0u;  // padding entry
+  }
+  __syncthreads();
+  if (bad) atomicOr(&extra[4], bad);
+
+  // ---- this thread's words --------------------------------------------------------
+  const uint32_t m = (uint32_t)tid % hx;
+  const uint32_t gl0 = (uint32_t)tid / hx;
+  const uint32_t m_up = (m + 1u == hx) ? 0u : m + 1u;
+  const uint32_t m_dn = (m == 0u) ? hx - 1u : m - 1u;
+  const uint32_t lp = (uint32_t)a.lp;
+  Bs4Walk wk;
+  wk.LY4 = LY4;
+  wk.Lz = Lz;
+  wk.lp_z = NDIM == 2 ? 0u : lp / LY4;
+  wk.lp_y = lp - wk.lp_z * LY4;
+  wk.z0 = NDIM == 2 ? 0u : gl0 / LY4;
+  wk.Y0 = gl0 - wk.z0 * LY4;
+  wk.base0 = (gl0 * hx + m) * RS * 4u;
+  wk.du = (m_up - m) * RS * 4u;
+  wk.dd = (m_dn - m) * RS * 4u;
+  wk.step = lp * hx * RS * 4u;
+  wk.row = hx * RS * 4u;
+  wk.plane = LY4 * wk.row;
+  wk.ci0 = 4u * gl0 * Lx + 2u * m;
+  wk.ci_step = 4u * lp * Lx;
+  wk.GL = GL;
+  wk.gl0 = gl0;
+  wk.lp = lp;
+  const bool active = tid < (int)(hx * lp);
+  const uint32_t valid16 = 0x1111u * ((1u << nvalid) - 1u);
+  char* lb = (char*)lds;
+
+  uint32_t fl[4] = {0u, 0u, 0u, 0u};
+  uint32_t n_blocks = 0u, n_draws = 0u;  // RNG statistics (STATS only)
+
+  for (int t = a.t_begin; t < a.t_end; ++t) {
+    const uint32_t* tr = a.thr + (size_t)t * NDIM;
+    const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
+    if (active) bs4_half<NDIM, 0, FLIPS, STATS>(lb, wk, a, t, quad, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+    __syncthreads();
+    if (active) bs4_half<NDIM, 1, FLIPS, STATS>(lb, wk, a, t, quad, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+    __syncthreads();
+  }
+
+  // ---- unsatisfied bonds of the colour-0 sites: energy -----------------------
+  if (active) {
+    uint32_t e[4] = {0u, 0u, 0u, 0u};
+    uint32_t base = wk.base0;
+    uint32_t Y = wk.Y0, z = wk.z0;
+    for (uint32_t gl = gl0; gl < GL; gl += lp) {
+      uint32_t s, u0, u1, u2;
+      bs4_bonds<NDIM, 0>(lb, base, wk, Y, z, s, u0, u1, u2);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const uint32_t mr = 0x1111u << b;
+        e[b] += __popc(u0 & mr) + 2u * __popc(u1 & mr) + 4u * __popc(u2 & mr);
+      }
+      base += wk.step;
+      Y += wk.lp_y;
+      z += wk.lp_z;
+      if (Y >= LY4) {
+        Y -= LY4;
+        z += 1u;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      atomicAdd(&extra[8 + b], e[b]);
+      if (FLIPS) atomicAdd(&extra[b], fl[b]);
+    }
+    // per-thread totals go straight to the 64-bit outputs
+    if (STATS && (n_blocks | n_draws)) {
+      atomicAdd(&a.stats[0], (unsigned long long)n_blocks);
+      atomicAdd(&a.stats[1], (unsigned long long)n_draws);
+    }
+  }
+  __syncthreads();
+
+  // ---- state out --------------------------------------------------------------
+  for (uint32_t i = tid; i < (uint32_t)L.n; i += B) {
+    const uint32_t line = i / Lx, x = i - line * Lx;
+    const uint32_t z = line / Ly, y = line - z * Ly;
+    const uint32_t p = (x + y + z) & 1u;
+    const uint32_t word = lds[((line >> 2) * hx + (x >> 1)) * RS + p];
+    const uint32_t j = line & 3u;
+    for (int b = 0; b < nvalid; ++b)
+      a.spins[(size_t)(r0 + b) * n + i] = ((word >> (4u * j + (uint32_t)b)) & 1u) ? (int8_t)1 : (int8_t)-1;
+  }
+  const int64_t n_edges = (int64_t)NDIM * L.n;
+  for (int b = tid; b < nvalid; b += B) {
+    const int r = r0 + b;
+    const bool invalid = (extra[4] >> b) & 1u;
+    const int64_t h = 2 * (int64_t)extra[8 + b] - n_edges;
+    if (a.flips) a.flips[r] = extra[b];
+    if (a.energy) a.energy[r] = invalid ? INT64_MIN : h;
+    if (a.cut) a.cut[r] = invalid ? INT64_MIN : (a.w_total - h) / 2;
+  }
+}
+
+
+}  // namespace bs4q
+}  // namespace ising

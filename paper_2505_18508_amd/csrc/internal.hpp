@@ -67,24 +67,29 @@ hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t 
                              int64_t* energy, hipStream_t stream);
 hipError_t launch_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, hipStream_t stream);
 
-// A prepared persistent launch over several instances (four-replica packing).
-struct I8BatchPlan {
+// A prepared persistent launch over several instances (four-replica
+// packings, chosen per instance: layouts[k] = ISING_LAYOUT_I8 or _BS4).
+struct BatchPlan {
   int ndim = 2;
-  void* d_inst = nullptr;     // per-instance kernel arguments
+  void* d_inst = nullptr;     // per-instance packing and kernel arguments
   void* d_items = nullptr;    // (instance, quad) work items, costliest first
   unsigned int* d_counter = nullptr;
   int n_items = 0;
   size_t lds = 0;
   int grid = 0, block = 0;
 };
-hipError_t build_i8_batch(const ising_graph* const* graphs, const SweepLaunch* launches, int n_inst, I8BatchPlan* plan);
-hipError_t run_i8_batch(const I8BatchPlan& plan, hipStream_t stream);
-void free_i8_batch(I8BatchPlan& plan);
+hipError_t build_batch(const ising_graph* const* graphs, const SweepLaunch* launches, const int* layouts, int n_inst,
+                       BatchPlan* plan);
+hipError_t run_batch(const BatchPlan& plan, hipStream_t stream);
+void free_batch(BatchPlan& plan);
 
 // LDS bytes one block of each sweep kernel needs for a lattice.
 size_t sweep_i8_lds_bytes(const Lattice& L);
 size_t sweep_bp32_lds_bytes(const Lattice& L);
 size_t sweep_bs4_lds_bytes(const Lattice& L);
+// The dynamic (state) part of that for the four-replica kernels.
+size_t sweep_i8_dyn_lds(const Lattice& L);
+size_t sweep_bs4_dyn_lds(const Lattice& L);
 // Block size a sweep kernel uses for a requested size (0 = default; 0
 // returned when the kernel cannot take the lattice).
 int sweep_i8_block(const Lattice& L, int requested);

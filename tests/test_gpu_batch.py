@@ -1,6 +1,8 @@
 """Persistent batches of uneven instances: every replica bit-identical to a
 single-instance run (itself pinned to the oracle), at small and full size,
-eagerly and replayed from a captured HIP graph."""
+eagerly and replayed from a captured HIP graph.  Instances whose rows are a
+multiple of 4 take the bit-sliced 4 x 4 routine, the others the byte-per-
+replica one, in the same launch."""
 import numpy as np
 import pytest
 
@@ -145,3 +147,27 @@ def test_batch_argument_errors(ising):
     with pytest.raises(ising.IsingError) as e:
         ising.Batch([g2], [dict(run, spins=s2, sweep_begin=3, sweep_end=2)])
     assert e.value.code == ising.E_ARG
+
+
+def test_mixed_and_forced_layouts_in_one_batch(ising):
+    """Forced i8 and bs4 instances next to AUTO ones (which take bs4 where the
+    rows allow it): every replica equals its single-instance run."""
+    graphs, runs = make_runs(ising, [([8, 6], 6, 21, 9, 300, 0, 300, "geometric", 0.05, 4.0),
+                                     ([8, 6], 6, 21, 9, 300, 0, 300, "geometric", 0.05, 4.0),
+                                     ([6, 8], 7, 22, 6, 250, 0, 250, "linear", 0.1, 3.0)])
+    runs[0]["layout"] = "i8"
+    runs[1]["layout"] = "bs4"
+    b = ising.Batch(graphs, runs)
+    b.run()
+    import torch
+
+    torch.cuda.synchronize()
+    for g, run in zip(graphs, runs):
+        assert_run_equal(run, single(ising, g, run))
+    b.close()
+    g = ising.create_graph([6, 8], 1)
+    s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
+    with pytest.raises(ising.IsingError) as e:
+        ising.Batch([g], [dict(seed=1, n_sweeps=10, spins=s, layout="bs4")])
+    assert e.value.code == ising.E_UNSUPPORTED
+
