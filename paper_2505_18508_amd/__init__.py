@@ -72,6 +72,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libising.so is not built (run paper_2505_18508_amd/build.py): %s" % LIB_PATH)
+        # torch ships its own HIP runtime under the same soname as the system
+        # one this library links against; whichever is loaded first serves the
+        # whole process, and torch works only with its own.  Loading torch
+        # first makes torch's streams, its allocations and this library's
+        # launches share that one runtime.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         L.ising_create_graph.argtypes = [i32, vp, u64, vp, ctypes.POINTER(vp)]

@@ -90,3 +90,18 @@ def test_host_argument_errors():
     assert ising.lib().ising_create_graph(2, d.ctypes.data, 1, None, ctypes.byref(h)) == ising.E_TOPOLOGY
     assert ising.lib().ising_create_graph(2, None, 1, None, ctypes.byref(h)) == ising.E_ARG
     ising.lib().ising_destroy_graph(None)  # NULL-safe
+
+
+def test_one_hip_runtime_in_the_process():
+    """Loading the library first (before any torch import) still leaves a
+    single HIP runtime mapped: torch's, which the library then shares."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2505_18508_amd as p; p.lib(); "
+            "m = open('/proc/self/maps').read(); "
+            "print(len(set(l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l)))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
