@@ -138,6 +138,13 @@ typedef struct {
                              /* Philox4x32-10 blocks it evaluated to [0] and the     */
                              /* number of attempts that needed a uniform (dE > 0 and */
                              /* a nonzero threshold) to [1]                          */
+  const uint32_t* replica_thresholds; /* device uint32 [R][degree/2] or NULL: replica */
+                             /* r runs every sweep of the window at its own fixed    */
+                             /* temperature, thresholds replica_thresholds[r][k-1]   */
+                             /* for dE = 4k, instead of the schedule's (replica      */
+                             /* exchange); layouts I8 and BS4 (AUTO picks one).      */
+                             /* Callers built against the struct without this field  */
+                             /* pass the smaller struct_size and get NULL.           */
 } ising_run_params;
 
 /*
@@ -191,6 +198,52 @@ int ising_schedule_beta(const ising_run_params* p, int32_t t, double* beta_out);
  * cross-checks: device uint32 ctr[m][4] in, device uint32 out[m][4] out.
  * Asynchronous on `stream`. */
 int ising_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Replica exchange (parallel tempering) on the same sweep kernels.  L ladders
+ * of K inverse temperatures beta_0 <= ... <= beta_{K-1}; replica slot
+ * r = l K + i starts at temperature i of ladder l.  Round q runs sweeps
+ * [qE, (q+1)E) with every replica at its own temperature, then one exchange
+ * pass over the adjacent pairs (k, k+1), k = q mod 2, q mod 2 + 2, ..., of
+ * every ladder: the replicas at beta_k and beta_{k+1} swap temperatures with
+ * probability min(1, exp((beta_k - beta_{k+1})(H_a - H_b))).  On an
+ * even-degree torus H_a - H_b = 4m; m <= 0 or equal temperatures accept
+ * without a draw, else accept iff u < min(2^32 - 1,
+ * floor(2^32 exp(-(beta_{k+1} - beta_k) 4m))) (host-computed table),
+ * u = word 0 of Philox(seed, (k, q, l, tag 4)).  Spins stay in their slots;
+ * only temperature labels move.
+ * ---------------------------------------------------------------------- */
+typedef struct ising_pt ising_pt;
+
+/*
+ * Prepare replica exchange on g (synchronous; allocates device tables).
+ *   n_temps K >= 2 and betas: host double [K], non-decreasing, >= 0;
+ *   adjacent distinct temperatures at least 1e-4 apart (the exchange table
+ *   of a pair has at most 65,536 entries).  n_ladders L >= 1; seed keys
+ *   both the sweeps and the exchanges.  The graph must outlive the handle.
+ */
+int ising_pt_create(const ising_graph* g, int32_t n_temps, const double* betas, int32_t n_ladders, uint64_t seed,
+                    ising_pt** out);
+
+/*
+ * Rounds [round_begin, round_begin + n_rounds) of sweeps_per_round sweeps
+ * each, on device int8 spins [L K][n] (canonical layout, in/out; Philox
+ * initial state when init_spins, which needs round_begin == 0).  cut_out /
+ * energy_out: device int64 [L K] or NULL, the final states' eq. (1) / (2)
+ * values.  Asynchronous on `stream`; the handle's labels advance with it.
+ */
+int ising_pt_run(ising_pt* pt, int8_t* spins, int32_t init_spins, int32_t round_begin, int32_t n_rounds,
+                 int32_t sweeps_per_round, int64_t* cut_out, int64_t* energy_out, void* stream);
+
+/*
+ * Labels and counters: temp_index_out device int32 [L K] (temperature index
+ * of every slot) or NULL, asynchronous on `stream`; accepted_out host
+ * uint64 [K - 1] (exchanges accepted per pair since creation) or NULL,
+ * synchronous.
+ */
+int ising_pt_state(const ising_pt* pt, int32_t* temp_index_out, uint64_t* accepted_out, void* stream);
+
+void ising_pt_destroy(ising_pt* pt); /* NULL-safe */
 
 /* ------------------------------------------------------------------------
  * Batches of uneven instances in one persistent launch.  Every (instance,

@@ -51,6 +51,9 @@ def lib():
                               ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                               ctypes.c_int, _i8p, _u32p, ctypes.c_void_p]
         L.orc_run.restype = ctypes.c_int
+        L.orc_run_fixed.argtypes = [ctypes.c_int, _i32p, _i8p, c_u64, c_i32, c_i32, c_i32, c_i32, _u32p,
+                                    ctypes.c_int, _i8p, _u32p]
+        L.orc_run_fixed.restype = ctypes.c_int
         L.orc_maxcut_bruteforce.argtypes = [c_i64, c_i64, _i32p, _i32p, _i8p, ctypes.POINTER(ctypes.c_uint64)]
         L.orc_maxcut_bruteforce.restype = c_i64
         _lib = L
@@ -161,6 +164,24 @@ def run(dims, w, seed, n_replicas, n_sweeps, begin=0, end=None, schedule=SCHED_L
     if rc != 0:
         raise ValueError("oracle rejected the run arguments")
     return (s, fl, fo) if return_fields else (s, fl)
+
+
+def run_fixed(dims, w, seed, rep_thr, begin, end, spins=None, replica_begin=0):
+    """Sweeps [begin, end) with replica r at its own fixed thresholds
+    rep_thr[r] (uint32 [R][deg/2]); spins=None: Philox initial state (begin
+    must be 0).  Returns (spins, flips)."""
+    d = _dims(dims)
+    n = n_sites(dims)
+    th = np.ascontiguousarray(rep_thr, np.uint32)
+    R = th.shape[0]
+    init = spins is None
+    s = np.zeros((R, n), np.int8) if init else np.array(spins, dtype=np.int8, copy=True, order="C")
+    fl = np.zeros(R, np.uint32)
+    rc = lib().orc_run_fixed(len(d), d, np.ascontiguousarray(w, np.int8), int(seed), int(replica_begin), R,
+                             int(begin), int(end), th, int(init), s, fl)
+    if rc != 0:
+        raise ValueError("oracle rejected the run arguments")
+    return s, fl
 
 
 def maxcut_bruteforce(dims, w):

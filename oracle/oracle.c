@@ -230,10 +230,14 @@ void orc_fields(int ndim, const int32_t* dims, const int8_t* w, const int8_t* sp
  * word (r & 3) of Philox(seed, (i, t, r>>2, TAG_METROPOLIS)).  Accepted flips
  * update the maintained fields of the neighbours: f_j -= 2 w_ij s_i(old).
  * ------------------------------------------------------------------------- */
-int orc_run(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
-            int32_t replica_begin, int32_t n_replicas, int32_t n_sweeps,
-            int32_t begin, int32_t end, int schedule, double beta0, double beta1,
-            const double* table, int init, int8_t* spins, uint32_t* flips, int32_t* fields_out) {
+/* The sweeps of orc_run and orc_run_fixed: replica rr runs at the schedule's
+ * beta_t, or, when rep_thr is given, with its own thresholds
+ * rep_thr[rr][k-1] (k = 1..deg/2) at every sweep. */
+static int run_core(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
+                    int32_t replica_begin, int32_t n_replicas, int32_t n_sweeps,
+                    int32_t begin, int32_t end, int schedule, double beta0, double beta1,
+                    const double* table, const uint32_t* rep_thr, int init, int8_t* spins,
+                    uint32_t* flips, int32_t* fields_out) {
     if (ndim != 2 && ndim != 3) return -1;
     for (int d = 0; d < ndim; ++d)
         if (dims[d] < 2 || (dims[d] & 1)) return -1;
@@ -265,8 +269,12 @@ int orc_run(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
             f[i] = acc;
         }
         for (int32_t t = begin; t < end; ++t) {
-            double beta = orc_beta(schedule, beta0, beta1, table, n_sweeps, t);
-            for (int k = 1; k <= deg / 2; ++k) thr[k] = orc_threshold(beta, k);
+            if (rep_thr) {
+                for (int k = 1; k <= deg / 2; ++k) thr[k] = rep_thr[(int64_t)rr * (deg / 2) + k - 1];
+            } else {
+                double beta = orc_beta(schedule, beta0, beta1, table, n_sweeps, t);
+                for (int k = 1; k <= deg / 2; ++k) thr[k] = orc_threshold(beta, k);
+            }
             for (int c = 0; c < 2; ++c) {
                 for (int64_t i = 0; i < n; ++i) {
                     if (colour[i] != c) continue;
@@ -293,6 +301,22 @@ int orc_run(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
     free(colour); free(f); free(thr);
     free_adjacency(&adj);
     return 0;
+}
+
+int orc_run(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
+            int32_t replica_begin, int32_t n_replicas, int32_t n_sweeps,
+            int32_t begin, int32_t end, int schedule, double beta0, double beta1,
+            const double* table, int init, int8_t* spins, uint32_t* flips, int32_t* fields_out) {
+    return run_core(ndim, dims, w, seed, replica_begin, n_replicas, n_sweeps, begin, end, schedule, beta0, beta1,
+                    table, NULL, init, spins, flips, fields_out);
+}
+
+int orc_run_fixed(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
+                  int32_t replica_begin, int32_t n_replicas, int32_t begin, int32_t end,
+                  const uint32_t* rep_thr, int init, int8_t* spins, uint32_t* flips) {
+    if (!rep_thr) return -1;
+    return run_core(ndim, dims, w, seed, replica_begin, n_replicas, end, begin, end, ORC_SCHED_LINEAR, 1.0, 1.0,
+                    NULL, rep_thr, init, spins, flips, NULL);
 }
 
 /* Exhaustive maximum of eq. (1) over all 2^n states. */

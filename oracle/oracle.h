@@ -71,6 +71,15 @@ int orc_run(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
             int32_t begin, int32_t end, int schedule, double beta0, double beta1,
             const double* table, int init, int8_t* spins, uint32_t* flips, int32_t* fields_out);
 
+/*
+ * As orc_run over sweeps [begin, end), but replica rr keeps its own fixed
+ * temperature: every sweep uses its thresholds rep_thr[rr][k-1], k = 1..deg/2
+ * (a replica-exchange round).  Returns 0, or -1 on bad arguments.
+ */
+int orc_run_fixed(int ndim, const int32_t* dims, const int8_t* w, uint64_t seed,
+                  int32_t replica_begin, int32_t n_replicas, int32_t begin, int32_t end,
+                  const uint32_t* rep_thr, int init, int8_t* spins, uint32_t* flips);
+
 /* Largest cut over all 2^n states (n <= 30); best state written as bits. */
 int64_t orc_maxcut_bruteforce(int64_t n, int64_t n_edges, const int32_t* edge_a,
                               const int32_t* edge_b, const int8_t* w, uint64_t* best_state);

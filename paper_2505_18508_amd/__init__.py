@@ -32,6 +32,7 @@ EXPORTED = [
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
     "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy", "ising_final_cut_score",
+    "ising_pt_create", "ising_pt_run", "ising_pt_state", "ising_pt_destroy",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -60,6 +61,7 @@ class RunParams(ctypes.Structure):
         ("block_threads", ctypes.c_int32),
         ("replica_offset", ctypes.c_int32),
         ("stats_out", ctypes.c_void_p),
+        ("replica_thresholds", ctypes.c_void_p),
     ]
 
 
@@ -110,9 +112,14 @@ def lib():
         L.ising_batch_destroy.argtypes = [vp]
         L.ising_batch_destroy.restype = None
         L.ising_final_cut_score.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.ising_pt_create.argtypes = [vp, i32, vp, i32, u64, ctypes.POINTER(vp)]
+        L.ising_pt_run.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp]
+        L.ising_pt_state.argtypes = [vp, vp, vp, vp]
+        L.ising_pt_destroy.argtypes = [vp]
+        L.ising_pt_destroy.restype = None
         for name in EXPORTED:
             if name not in ("ising_destroy_graph", "ising_last_error", "ising_mlp_workspace_floats",
-                            "ising_batch_destroy"):
+                            "ising_batch_destroy", "ising_pt_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         L.ising_mlp_workspace_floats.restype = i64
         _lib = L
@@ -199,7 +206,7 @@ def generate_weights(dims, weight_seed):
 
 def make_params(seed, n_replicas, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,
                 beta1=3.0, beta_table=None, init_spins=True, layout="auto", block_threads=0, replica_offset=0,
-                stats=None):
+                stats=None, replica_thresholds=None):
     """RunParams plus the objects whose memory it points to (keep both alive)."""
     p = RunParams()
     p.struct_size = ctypes.sizeof(RunParams)
@@ -220,6 +227,7 @@ def make_params(seed, n_replicas, n_sweeps, sweep_begin=0, sweep_end=None, sched
     p.block_threads = int(block_threads)
     p.replica_offset = int(replica_offset)
     p.stats_out = None if stats is None else _ptr(stats).value
+    p.replica_thresholds = None if replica_thresholds is None else _ptr(replica_thresholds).value
     return p, keep
 
 
@@ -233,15 +241,18 @@ def select_layout(graph, n_replicas, n_sweeps=1, layout="auto", block_threads=0)
 
 def run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,
                beta1=3.0, beta_table=None, init_spins=True, layout="auto", cut=None, energy=None, flips=None,
-               block_threads=0, replica_offset=0, stats=None, stream=None):
+               block_threads=0, replica_offset=0, stats=None, stream=None, replica_thresholds=None):
     """ising_run_trials on device tensors: spins int8 [R][n] (in/out); cut,
-    energy int64 [R], flips uint32/int32 [R], stats int64 [2] optional.
-    Asynchronous."""
+    energy int64 [R], flips uint32/int32 [R], stats int64 [2] optional;
+    replica_thresholds uint32/int32 [R][degree/2] (each replica at its own
+    fixed temperature) optional.  Asynchronous."""
     R = spins.shape[0]
     if spins.dim() != 2 or spins.shape[1] != graph.n:
         raise ValueError("spins must be [R][%d]" % graph.n)
+    if replica_thresholds is not None and tuple(replica_thresholds.shape) != (R, graph.degree // 2):
+        raise ValueError("replica_thresholds must be [R][%d]" % (graph.degree // 2))
     p, keep = make_params(seed, R, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1, beta_table,
-                          init_spins, layout, block_threads, replica_offset, stats)
+                          init_spins, layout, block_threads, replica_offset, stats, replica_thresholds)
     _check(lib().ising_run_trials(graph.handle, ctypes.byref(p), _ptr(spins), _ptr(cut), _ptr(energy), _ptr(flips),
                                   _stream(stream)))
     del keep
@@ -392,3 +403,51 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class PT:
+    """Replica exchange (ising_pt_*): L ladders of K inverse temperatures on
+    one graph, L K replica slots.  run() advances rounds of sweeps plus one
+    exchange pass each; labels() gives every slot's temperature index."""
+
+    def __init__(self, graph, betas, n_ladders, seed):
+        b = np.ascontiguousarray(betas, np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().ising_pt_create(graph.handle, len(b), b.ctypes.data, int(n_ladders), int(seed), ctypes.byref(h)))
+        self._h = h
+        self.graph, self.betas, self.n_ladders = graph, b, int(n_ladders)
+        self.n_replicas = len(b) * self.n_ladders
+
+    def run(self, spins, n_rounds, sweeps_per_round, round_begin=0, init_spins=False, cut=None, energy=None,
+            stream=None):
+        if spins.dim() != 2 or spins.shape != (self.n_replicas, self.graph.n):
+            raise ValueError("spins must be [%d][%d]" % (self.n_replicas, self.graph.n))
+        _check(lib().ising_pt_run(self._h, _ptr(spins), 1 if init_spins else 0, int(round_begin), int(n_rounds),
+                                  int(sweeps_per_round), _ptr(cut), _ptr(energy), _stream(stream)))
+
+    def labels(self, out=None, stream=None):
+        """Temperature index of every slot (device int32 [L K])."""
+        import torch
+
+        if out is None:
+            out = torch.zeros(self.n_replicas, dtype=torch.int32, device="cuda")
+        _check(lib().ising_pt_state(self._h, _ptr(out), None, _stream(stream)))
+        return out
+
+    def accepted(self):
+        """Exchanges accepted per adjacent pair since creation (host uint64 [K-1]); synchronises."""
+        acc = np.zeros(len(self.betas) - 1, np.uint64)
+        _check(lib().ising_pt_state(self._h, None, acc.ctypes.data, None))
+        return acc
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ising_pt_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

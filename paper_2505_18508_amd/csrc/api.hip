@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -92,11 +93,19 @@ std::vector<uint8_t> site_weight_bits(const Lattice& L, const std::vector<int8_t
   return bits;
 }
 
+// struct_size of ising_run_params before replica_thresholds was appended
+constexpr size_t kParamsSizeV1 = offsetof(ising_run_params, replica_thresholds);
+
+// The per-replica thresholds of p, NULL for callers of the older struct.
+const uint32_t* replica_thr(const ising_run_params* p) {
+  return p->struct_size >= sizeof(ising_run_params) ? p->replica_thresholds : nullptr;
+}
+
 int check_params(const ising_run_params* p) {
   if (!p) return fail(ISING_E_ARG, "params is NULL");
-  if (p->struct_size != sizeof(ising_run_params))
-    return fail(ISING_E_ARG, "params.struct_size is %u, this library expects %zu", p->struct_size,
-                sizeof(ising_run_params));
+  if (p->struct_size != sizeof(ising_run_params) && p->struct_size != kParamsSizeV1)
+    return fail(ISING_E_ARG, "params.struct_size is %u, this library expects %zu (or %zu)", p->struct_size,
+                sizeof(ising_run_params), kParamsSizeV1);
   if (p->n_sweeps < 1) return fail(ISING_E_ARG, "n_sweeps must be >= 1");
   switch (p->schedule) {
     case ISING_SCHED_LINEAR:
@@ -131,10 +140,7 @@ double schedule_beta(const ising_run_params* p, int32_t t) {
   return p->beta0 * std::pow(p->beta1 / p->beta0, frac);
 }
 
-uint32_t accept_threshold(double beta, int k) {
-  const double scaled = std::ldexp(std::exp(-(double)(4 * k) * beta), 32);
-  return scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
-}
+using ising::accept_threshold;
 
 void fill_thresholds(const ising_run_params* p, int kmax, uint32_t* out) {
   for (int32_t t = 0; t < p->n_sweeps; ++t) {
@@ -215,14 +221,7 @@ int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t
   return ISING_OK;
 }
 
-int check_device(const ising_graph* g) {
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-  if (dev != g->device)
-    return fail(ISING_E_STATE, "graph lives on device %d but device %d is current", g->device, dev);
-  return ISING_OK;
-}
+using ising::check_device;
 
 }  // namespace
 
@@ -241,6 +240,20 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int fail_hip(hipError_t e, const char* what) { return fail(ISING_E_HIP, "%s: %s", what, hipGetErrorString(e)); }
+
+uint32_t accept_threshold(double beta, int k) {
+  const double scaled = std::ldexp(std::exp(-(double)(4 * k) * beta), 32);
+  return scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)std::floor(scaled);
+}
+
+int check_device(const ising_graph* g) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+  if (dev != g->device)
+    return fail(ISING_E_STATE, "graph lives on device %d but device %d is current", g->device, dev);
+  return ISING_OK;
+}
 
 }  // namespace ising
 
@@ -387,6 +400,10 @@ int check_run(const ising_graph* g, const ising_run_params* p, const int8_t* spi
   const bool bs4_fits = ising::sweep_bs4_block(g->lat, p->block_threads) > 0 &&
                         ising::sweep_bs4_lds_bytes(g->lat) <= dev.lds_per_block;
   int layout = p->layout;
+  const bool per_replica = replica_thr(p) != nullptr;
+  if (per_replica && layout == ISING_LAYOUT_AUTO) layout = bs4_fits ? ISING_LAYOUT_BS4 : ISING_LAYOUT_I8;
+  if (per_replica && layout != ISING_LAYOUT_BS4 && layout != ISING_LAYOUT_I8)
+    return fail(ISING_E_UNSUPPORTED, "per-replica thresholds need layout I8 or BS4");
   if (layout == ISING_LAYOUT_AUTO) {
     // 32 replicas per block wins per attempt, but only fills the chip with at
     // least one group per compute unit; below that, four replicas per block,
@@ -422,6 +439,7 @@ ising::SweepLaunch make_launch(const ising_run_params* p, const uint32_t* d_thr,
                                int64_t* energy, uint32_t* flips) {
   ising::SweepLaunch s;
   s.d_thr = d_thr;
+  s.rep_thr = replica_thr(p);
   s.spins = spins;
   s.cut = cut;
   s.energy = energy;
@@ -466,8 +484,10 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
   hipStream_t st = (hipStream_t)stream;
   uint32_t* d_thr = nullptr;
   bool owned = false;
-  rc = threshold_table(g, p, st, &d_thr, &owned);
-  if (rc) return rc;
+  if (!replica_thr(p)) {  // per-replica thresholds replace the schedule's table
+    rc = threshold_table(g, p, st, &d_thr, &owned);
+    if (rc) return rc;
+  }
   const ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
   hipError_t e;
   if (layout == ISING_LAYOUT_STREAM) {

@@ -44,58 +44,64 @@ __device__ __forceinline__ uint32_t lt_shift_in(uint32_t c, uint32_t x, uint32_t
 }
 
 // The four words of one Philox block shifted into LEV compare chains at once
-// (word 3 first): c_k = 16 c_k + bits (u_3 < T_k, ..., u_0 < T_k).  One asm
-// block per Philox block keeps the carry sequence free of inserted waits.
+// (word 3 first), word b against its own thresholds T_k[b] (the four
+// replicas of a quad may run at different temperatures; all are uniform
+// over the block): c_k = 16 c_k + bits (u_3 < T_k[3], ..., u_0 < T_k[0]).
+// One asm block per Philox block keeps the carry sequence free of inserted
+// waits.
+template <int LEV>
+__device__ __forceinline__ void lt_shift_in4(uint32_t& c1, uint32_t& c2, uint32_t& c3, const uint32_t* u,
+                                             const uint32_t* T1, const uint32_t* T2, const uint32_t* T3) {
+  uint32_t d;
+  if (LEV == 1) {
+    asm("v_subrev_co_u32_e32 %0, vcc, %2, %6\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %3, %7\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %4, %8\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %5, %9\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc"
+        : "=&v"(d), "+v"(c1)
+        : "s"(T1[3]), "s"(T1[2]), "s"(T1[1]), "s"(T1[0]), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+        : "vcc");
+  } else if (LEV == 2) {
+    asm("v_subrev_co_u32_e32 %0, vcc, %3, %11\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %7, %11\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %4, %12\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %8, %12\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %5, %13\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %9, %13\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %6, %14\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %10, %14\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc"
+        : "=&v"(d), "+v"(c1), "+v"(c2)
+        : "s"(T1[3]), "s"(T1[2]), "s"(T1[1]), "s"(T1[0]), "s"(T2[3]), "s"(T2[2]), "s"(T2[1]), "s"(T2[0]),
+          "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+        : "vcc");
+  } else {
+#pragma unroll
+    for (int b = 3; b >= 0; --b) {
+      c1 = lt_shift_in(c1, u[b], T1[b]);
+      c2 = lt_shift_in(c2, u[b], T2[b]);
+      c3 = lt_shift_in(c3, u[b], T3[b]);
+    }
+  }
+}
+
+// The same with one threshold per level for all four words.
 template <int LEV>
 __device__ __forceinline__ void lt_shift_in4(uint32_t& c1, uint32_t& c2, uint32_t& c3, const uint32_t* u, uint32_t T1,
                                              uint32_t T2, uint32_t T3) {
-  uint32_t d;
-  if (LEV == 1) {
-    asm("v_subrev_co_u32_e32 %0, vcc, %2, %3\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %2, %4\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %2, %5\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %2, %6\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc"
-        : "=&v"(d), "+v"(c1)
-        : "s"(T1), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
-        : "vcc");
-  } else if (LEV == 2) {
-    asm("v_subrev_co_u32_e32 %0, vcc, %3, %5\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %4, %5\n\t"
-        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %3, %6\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %4, %6\n\t"
-        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %3, %7\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %4, %7\n\t"
-        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %3, %8\n\t"
-        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
-        "v_subrev_co_u32_e32 %0, vcc, %4, %8\n\t"
-        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc"
-        : "=&v"(d), "+v"(c1), "+v"(c2)
-        : "s"(T1), "s"(T2), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
-        : "vcc");
-  } else {
-    c1 = lt_shift_in(c1, u[3], T1);
-    c2 = lt_shift_in(c2, u[3], T2);
-    c3 = lt_shift_in(c3, u[3], T3);
-    c1 = lt_shift_in(c1, u[2], T1);
-    c2 = lt_shift_in(c2, u[2], T2);
-    c3 = lt_shift_in(c3, u[2], T3);
-    c1 = lt_shift_in(c1, u[1], T1);
-    c2 = lt_shift_in(c2, u[1], T2);
-    c3 = lt_shift_in(c3, u[1], T3);
-    c1 = lt_shift_in(c1, u[0], T1);
-    c2 = lt_shift_in(c2, u[0], T2);
-    c3 = lt_shift_in(c3, u[0], T3);
-  }
+  const uint32_t t1[4] = {T1, T1, T1, T1}, t2[4] = {T2, T2, T2, T2}, t3[4] = {T3, T3, T3, T3};
+  lt_shift_in4<LEV>(c1, c2, c3, u, t1, t2, t3);
 }
 
 }  // namespace ising

@@ -58,7 +58,8 @@ struct Bs4Args {
   Lattice lat;
   const uint8_t* wbits;  // colour-split order, bit d set: weight of direction d (+x,-x,+y,-y,+z,-z) is -1
   int8_t* spins;
-  const uint32_t* thr;
+  const uint32_t* thr;      // schedule thresholds [S][NDIM]
+  const uint32_t* rep_thr;  // or per-replica fixed thresholds [R][NDIM]
   int64_t* cut;
   int64_t* energy;
   uint32_t* flips;
@@ -120,25 +121,47 @@ __device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const 
   bond_count3<DEG>(x, u0, u1, u2);
 }
 
+// Thresholds of the quad's four replicas for one sweep: T[k-1][b] for
+// dE = 4k and replica b (equal for all b under a schedule); lev = length of
+// the prefix of levels with a nonzero threshold for some replica (thresholds
+// decrease with k); m[k-1] = lanes 4 j + b of the replicas with T[k-1][b] != 0.
+struct QuadThr {
+  uint32_t T[3][4];
+  uint32_t m[3];
+  int lev;
+};
+
+__device__ __forceinline__ void quad_thr_finish(QuadThr& th) {
+  th.lev = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    uint32_t mk = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) mk |= th.T[k][b] ? (0x1111u << b) : 0u;
+    th.m[k] = mk;
+    if (mk && th.lev == k) th.lev = k + 1;
+  }
+}
+
 // The draws of a word's four sites and their compares against the first LEV
-// thresholds: bit 4 j + r of c_k = (Philox word r of site j) < T_k.  Site
-// j's canonical index: line 4 gl + j, x = 2m + (q ^ (j & 1)).
+// thresholds: bit 4 j + r of c_k = (Philox word r of site j) < T_k of
+// replica r.  Site j's canonical index: line 4 gl + j, x = 2m + (q ^ (j & 1)).
 template <int LEV>
 __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t Lx, uint32_t q, uint32_t t,
-                                          uint32_t quad, uint32_t T1, uint32_t T2, uint32_t T3, uint32_t& c1,
-                                          uint32_t& c2, uint32_t& c3) {
+                                          uint32_t quad, const QuadThr& th, uint32_t& c1, uint32_t& c2,
+                                          uint32_t& c3) {
 #pragma unroll
   for (int j = 3; j >= 0; --j) {
     const uint32_t ci = ci0 + (uint32_t)j * Lx + (q ^ (uint32_t)(j & 1));
     const u32x4 r = philox_lane_c0(seed, ci, t, quad, kTagMetropolis);
-    lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
+    lt_shift_in4<LEV>(c1, c2, c3, r.v, th.T[0], th.T[1], th.T[2]);
   }
 }
 
 // One half-sweep of colour P over this thread's words.
 template <int NDIM, int P, bool FLIPS, bool STATS>
 __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4Args& a, int t, uint32_t quad,
-                                         uint32_t T1, uint32_t T2, uint32_t T3, uint32_t valid16, uint32_t* fl,
+                                         const QuadThr& th, uint32_t valid16, uint32_t* fl,
                                          uint32_t& n_blocks, uint32_t& n_draws) {
   const uint32_t Lx = (uint32_t)a.lat.Lx;
   uint32_t base = wk.base0, ci0 = wk.ci0;
@@ -159,17 +182,16 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
       k3 = ~(u0 | u1 | u2);
     }
     uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-    if (T1 != 0u) {
+    if (th.lev != 0) {
       const uint32_t q = ((uint32_t)P + z) & 1u;
-      // thresholds decrease with k, so the nonzero ones are a prefix
-      if (T2 == 0u)
-        bs4_draws<1>(a.seed, ci0, Lx, q, (uint32_t)t, quad, T1, T2, T3, c1, c2, c3);
-      else if (NDIM == 2 || T3 == 0u)
-        bs4_draws<2>(a.seed, ci0, Lx, q, (uint32_t)t, quad, T1, T2, T3, c1, c2, c3);
+      if (th.lev == 1)
+        bs4_draws<1>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, c1, c2, c3);
+      else if (NDIM == 2 || th.lev == 2)
+        bs4_draws<2>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, c1, c2, c3);
       else
-        bs4_draws<3>(a.seed, ci0, Lx, q, (uint32_t)t, quad, T1, T2, T3, c1, c2, c3);
+        bs4_draws<3>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, c1, c2, c3);
       if (STATS) {
-        const uint32_t need = (k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & valid16;
+        const uint32_t need = ((k1 & th.m[0]) | (k2 & th.m[1]) | (k3 & th.m[2])) & valid16;
         n_blocks += 4u;
         n_draws += __popc(need);
       }
@@ -286,12 +308,27 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   uint32_t fl[4] = {0u, 0u, 0u, 0u};
   uint32_t n_blocks = 0u, n_draws = 0u;  // RNG statistics (STATS only)
 
+  QuadThr th;
+  if (a.rep_thr) {  // each replica at its own temperature for the whole window
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        th.T[k][b] = (k < NDIM && b < nvalid) ? a.rep_thr[(size_t)(r0 + b) * NDIM + k] : 0u;
+    quad_thr_finish(th);
+  }
   for (int t = a.t_begin; t < a.t_end; ++t) {
-    const uint32_t* tr = a.thr + (size_t)t * NDIM;
-    const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
-    if (active) bs4_half<NDIM, 0, FLIPS, STATS>(lb, wk, a, t, quad, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+    if (!a.rep_thr) {
+      const uint32_t* tr = a.thr + (size_t)t * NDIM;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) th.T[k][b] = k < NDIM ? tr[k] : 0u;
+      quad_thr_finish(th);
+    }
+    if (active) bs4_half<NDIM, 0, FLIPS, STATS>(lb, wk, a, t, quad, th, valid16, fl, n_blocks, n_draws);
     __syncthreads();
-    if (active) bs4_half<NDIM, 1, FLIPS, STATS>(lb, wk, a, t, quad, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+    if (active) bs4_half<NDIM, 1, FLIPS, STATS>(lb, wk, a, t, quad, th, valid16, fl, n_blocks, n_draws);
     __syncthreads();
   }
 

@@ -49,14 +49,16 @@ constexpr int kLutWords = 24;                  // (0x5C >> 2) + 1
 // bit of the word holding the weight sign of direction slot d
 constexpr int kWPos[6] = {0, 1, 5, 7, 8, 9};
 // LDS beside the state words: threshold tables, counters, a queue slot
-constexpr size_t kStaticLds = (2 * kLutWords + kExtraWords + 4) * 4;
+constexpr int kLutSet = 4 * kLutWords;         // one table per replica byte
+constexpr size_t kStaticLds = (2 * kLutSet + kExtraWords + 4) * 4;
 
 
 struct I8Args {
   Lattice lat;
   const uint8_t* wbits;
   int8_t* spins;
-  const uint32_t* thr;
+  const uint32_t* thr;      // schedule thresholds [S][NDIM]
+  const uint32_t* rep_thr;  // or per-replica fixed thresholds [R][NDIM]
   int64_t* cut;
   int64_t* energy;
   uint32_t* flips;
@@ -138,7 +140,7 @@ __device__ __forceinline__ uint32_t i8_half(const I8Args& a, const I8Walk& wk, u
   constexpr uint32_t kGeBias = (uint32_t)((1 << kSpinBit) - 2 * DEG) * kOnes;  // + 4c: spin bit iff c >= deg/2
   constexpr uint32_t kLeBias = (uint32_t)((1 << kSpinBit) + 2 * DEG) * kOnes;  // - 4c: spin bit iff c <= deg/2
   const Lattice& L = a.lat;
-  const char* tab = (const char*)(lut + BUF * kLutWords);
+  const char* tab = (const char*)(lut + BUF * kLutSet);  // then byte b's table at + 4 b kLutWords bytes
   char* st = (char*)lds;
   const uint32_t hx = (uint32_t)L.hx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz;
   const uint32_t lp = (uint32_t)a.lp;
@@ -168,9 +170,9 @@ __device__ __forceinline__ uint32_t i8_half(const I8Args& a, const I8Walk& wk, u
     const uint32_t w = *(const uint32_t*)(st + own);
     const uint32_t wm = w & kLutSel;
     const uint32_t T0 = *(const uint32_t*)(tab + (wm & 0xFFu));
-    const uint32_t T1 = *(const uint32_t*)(tab + ((wm >> 8) & 0xFFu));
-    const uint32_t T2 = *(const uint32_t*)(tab + ((wm >> 16) & 0xFFu));
-    const uint32_t T3 = *(const uint32_t*)(tab + (wm >> 24));
+    const uint32_t T1 = *(const uint32_t*)(tab + 4 * kLutWords + ((wm >> 8) & 0xFFu));
+    const uint32_t T2 = *(const uint32_t*)(tab + 8 * kLutWords + ((wm >> 16) & 0xFFu));
+    const uint32_t T3 = *(const uint32_t*)(tab + 12 * kLutWords + (wm >> 24));
     // dE <= 0: c >= deg/2 for spin +1, c <= deg/2 for spin -1
     const uint32_t c4 = w & kCnt;
     const uint32_t ge = c4 + kGeBias, le = kLeBias - c4;
@@ -232,7 +234,7 @@ __device__ __forceinline__ uint32_t i8_half(const I8Args& a, const I8Walk& wk, u
 }
 
 // One replica quad (local replicas r0 .. r0+3) for the window of a.  Called
-// by every thread of a block; lds holds the n state words, lut 2 kLutWords
+// by every thread of a block; lds holds the n state words, lut 2 kLutSet
 // threshold words and extra kExtraWords words.
 template <int NDIM, bool STATS>
 __device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t* lds, uint32_t* lut,
@@ -312,23 +314,28 @@ __device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t*
   __syncthreads();
 
   // ---- the window of sweeps -----------------------------------------------
-  // Per-sweep threshold table, double-buffered: entry spin << 4 | c holds
-  // T_k(t) of that state when its dE = 4k > 0, else 0 (a dE <= 0 state flips
-  // without a draw).  Sweep t+1's table is written during sweep t's first
-  // half; two barriers separate it from its first reader.
+  // Per-sweep threshold tables, one per replica byte, double-buffered: entry
+  // spin << 4 | c of byte b's table holds that replica's T_k(t) when the
+  // state's dE = 4k > 0, else 0 (a dE <= 0 state flips without a draw).
+  // Under a schedule the four tables are equal; with per-replica fixed
+  // thresholds they differ and do not change.  Sweep t+1's tables are
+  // written during sweep t's first half; two barriers separate them from
+  // their first reader.
   auto fill_lut = [&](uint32_t* dst, int t) {
-    const uint32_t* tr = a.thr + (size_t)t * NDIM;
-    for (int idx = tid; idx < kLutWords; idx += B) {
+    for (int idx = tid; idx < kLutSet; idx += B) {
+      const int b = idx / kLutWords, e = idx - b * kLutWords;
+      const uint32_t* tr = a.rep_thr ? a.rep_thr + (size_t)(r0 + min(b, nvalid - 1)) * NDIM
+                                     : a.thr + (size_t)t * NDIM;
       uint32_t v = 0u;
-      const int c = idx & 7;
-      if ((idx & 8) == 0 && c <= DEG) {
-        const int k = (idx & 16) ? NDIM - c : c - NDIM;  // dE = 4k
+      const int c = e & 7;
+      if ((e & 8) == 0 && c <= DEG) {
+        const int k = (e & 16) ? NDIM - c : c - NDIM;  // dE = 4k
         if (k >= 1 && k <= NDIM) v = tr[k - 1];
       }
       dst[idx] = v;
     }
   };
-  fill_lut(lut + (a.t_begin & 1) * kLutWords, a.t_begin);
+  fill_lut(lut + (a.t_begin & 1) * kLutSet, a.t_begin);
   __syncthreads();
 
   I8Walk wk;
@@ -355,7 +362,7 @@ __device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t*
   for (int t = a.t_begin; t < a.t_end; ++t) {
     uint32_t fc_lo = 0u, fc_hi = 0u;  // flips, packed 16-bit lanes (bytes 0,2 / 1,3)
     for (int p = 0; p < 2; ++p) {
-      if (p == 0 && t + 1 < a.t_end) fill_lut(lut + ((t + 1) & 1) * kLutWords, t + 1);
+      if (p == 0 && t + 1 < a.t_end) fill_lut(lut + ((t + 1) & 1) * kLutSet, t + 1);
       uint32_t fc8 = 0u;  // flips this half-sweep, packed bytes
       if (active) {
         if constexpr (NDIM == 2) {

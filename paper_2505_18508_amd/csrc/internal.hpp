@@ -36,10 +36,16 @@ namespace ising {
 // Record a message for ising_last_error() and return code.
 int fail(int code, const char* fmt, ...);
 int fail_hip(hipError_t e, const char* what);
+// Metropolis threshold of an energy increase 4k at inverse temperature beta:
+// accept iff u < min(2^32 - 1, floor(2^32 exp(-4 k beta))), u a Philox word.
+uint32_t accept_threshold(double beta, int k);
+// ISING_E_STATE unless the graph's device is the current one.
+int check_device(const ising_graph* g);
 
 // Work description of one sweep-kernel launch (device pointers).
 struct SweepLaunch {
-  const uint32_t* d_thr;  // full-schedule threshold table [S][kmax]
+  const uint32_t* d_thr;  // full-schedule threshold table [S][kmax] (unused with rep_thr)
+  const uint32_t* rep_thr;  // per-replica fixed thresholds [R][kmax] or null
   int8_t* spins;
   int64_t* cut;
   int64_t* energy;

@@ -21,6 +21,7 @@ constexpr uint32_t kPhiloxWeylB = 0xBB67AE85u;
 constexpr uint32_t kTagMetropolis = 0u;
 constexpr uint32_t kTagInit = 1u;
 constexpr uint32_t kTagWeight = 2u;
+constexpr uint32_t kTagExchange = 4u;  // replica-exchange decisions (3 keys the network's initial weights)
 
 struct u32x4 {
   uint32_t v[4];

@@ -42,7 +42,7 @@ template <int NDIM>
 __global__ void __launch_bounds__(kBatchBlock) k_sweep_batch(const BatchInst* inst, const BatchItem* items, int n_items,
                                                              unsigned int* counter) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint32_t lut[2 * i8q::kLutWords];
+  __shared__ uint32_t lut[2 * i8q::kLutSet];
   __shared__ uint32_t extra[i8q::kExtraWords];
   __shared__ int next;
   for (;;) {
@@ -88,6 +88,7 @@ hipError_t build_batch(const ising_graph* const* graphs, const SweepLaunch* laun
       a.wbits = g->d_wbits;
       a.spins = s.spins;
       a.thr = s.d_thr;
+      a.rep_thr = s.rep_thr;
       a.cut = s.cut;
       a.energy = s.energy;
       a.flips = s.flips;

@@ -52,6 +52,7 @@ hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStrea
   a.wbits = g->d_wbits;
   a.spins = s.spins;
   a.thr = s.d_thr;
+  a.rep_thr = s.rep_thr;
   a.cut = s.cut;
   a.energy = s.energy;
   a.flips = s.flips;

@@ -14,7 +14,7 @@ using namespace i8q;
 template <int NDIM, bool STATS>
 __global__ void __launch_bounds__(kMaxBlock) k_sweep_i8(I8Args a) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint32_t lut[2 * kLutWords];
+  __shared__ uint32_t lut[2 * kLutSet];
   __shared__ uint32_t extra[kExtraWords];
   i8_quad<NDIM, STATS>(a, blockIdx.x * 4, lds, lut, extra);
 }
@@ -52,6 +52,7 @@ hipError_t launch_sweep_i8(const ising_graph* g, const SweepLaunch& s, hipStream
   a.wbits = g->d_wbits;
   a.spins = s.spins;
   a.thr = s.d_thr;
+  a.rep_thr = s.rep_thr;
   a.cut = s.cut;
   a.energy = s.energy;
   a.flips = s.flips;
