@@ -142,7 +142,8 @@ typedef struct {
                              /* r runs every sweep of the window at its own fixed    */
                              /* temperature, thresholds replica_thresholds[r][k-1]   */
                              /* for dE = 4k, instead of the schedule's (replica      */
-                             /* exchange); layouts I8 and BS4 (AUTO picks one).      */
+                             /* exchange); layouts I8 and BS4 (AUTO picks one);      */
+                             /* stats_out must then be NULL.                         */
                              /* Callers built against the struct without this field  */
                              /* pass the smaller struct_size and get NULL.           */
 } ising_run_params;

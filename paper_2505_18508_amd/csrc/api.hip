@@ -404,6 +404,8 @@ int check_run(const ising_graph* g, const ising_run_params* p, const int8_t* spi
   if (per_replica && layout == ISING_LAYOUT_AUTO) layout = bs4_fits ? ISING_LAYOUT_BS4 : ISING_LAYOUT_I8;
   if (per_replica && layout != ISING_LAYOUT_BS4 && layout != ISING_LAYOUT_I8)
     return fail(ISING_E_UNSUPPORTED, "per-replica thresholds need layout I8 or BS4");
+  if (per_replica && p->stats_out)
+    return fail(ISING_E_UNSUPPORTED, "RNG statistics are not collected with per-replica thresholds");
   if (layout == ISING_LAYOUT_AUTO) {
     // 32 replicas per block wins per attempt, but only fills the chip with at
     // least one group per compute unit; below that, four replicas per block,

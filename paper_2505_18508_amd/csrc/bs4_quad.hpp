@@ -132,15 +132,14 @@ struct QuadThr {
 };
 
 __device__ __forceinline__ void quad_thr_finish(QuadThr& th) {
-  th.lev = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     uint32_t mk = 0u;
 #pragma unroll
     for (int b = 0; b < 4; ++b) mk |= th.T[k][b] ? (0x1111u << b) : 0u;
     th.m[k] = mk;
-    if (mk && th.lev == k) th.lev = k + 1;
   }
+  th.lev = th.m[0] ? (th.m[1] ? (th.m[2] ? 3 : 2) : 1) : 0;
 }
 
 // The draws of a word's four sites and their compares against the first LEV
@@ -216,7 +215,9 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
 // One replica quad (local replicas r0 .. r0+3) for the window of a.  Called
 // by every thread of a block; lds holds sweep_bs4_lds_bytes(a.lat) - 64
 // bytes of records and extra kExtraWords words.
-template <int NDIM, bool FLIPS, bool STATS>
+// PT: the replicas run at their own fixed temperatures (a.rep_thr) instead
+// of the schedule's (a.thr).
+template <int NDIM, bool FLIPS, bool STATS, bool PT = false>
 __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_t* lds, uint32_t* extra) {
   constexpr int DEG = 2 * NDIM;
   constexpr uint32_t RS = (uint32_t)rec_words<NDIM>();
@@ -309,7 +310,7 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   uint32_t n_blocks = 0u, n_draws = 0u;  // RNG statistics (STATS only)
 
   QuadThr th;
-  if (a.rep_thr) {  // each replica at its own temperature for the whole window
+  if (PT) {  // each replica at its own temperature for the whole window
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -317,14 +318,22 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         th.T[k][b] = (k < NDIM && b < nvalid) ? a.rep_thr[(size_t)(r0 + b) * NDIM + k] : 0u;
     quad_thr_finish(th);
   }
+  // under a schedule the next sweep's thresholds are loaded a sweep ahead,
+  // so no wave waits for them after the barrier
+  uint32_t tn[3] = {0u, 0u, 0u};
+  if (!PT)
+#pragma unroll
+    for (int k = 0; k < NDIM; ++k) tn[k] = a.thr[(size_t)a.t_begin * NDIM + k];
   for (int t = a.t_begin; t < a.t_end; ++t) {
-    if (!a.rep_thr) {
-      const uint32_t* tr = a.thr + (size_t)t * NDIM;
+    if (!PT) {
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) th.T[k][b] = k < NDIM ? tr[k] : 0u;
+        for (int b = 0; b < 4; ++b) th.T[k][b] = tn[k];
       quad_thr_finish(th);
+      const int tnext = min(t + 1, a.t_end - 1);  // unconditional: no branch to merge
+#pragma unroll
+      for (int k = 0; k < NDIM; ++k) tn[k] = a.thr[(size_t)tnext * NDIM + k];
     }
     if (active) bs4_half<NDIM, 0, FLIPS, STATS>(lb, wk, a, t, quad, th, valid16, fl, n_blocks, n_draws);
     __syncthreads();

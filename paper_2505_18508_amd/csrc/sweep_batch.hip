@@ -53,8 +53,10 @@ __global__ void __launch_bounds__(kBatchBlock) k_sweep_batch(const BatchInst* in
     if (it >= n_items) break;
     const BatchItem bi = items[it];
     const BatchInst& I = inst[bi.inst];
-    if (I.bs4)
-      bs4q::bs4_quad<NDIM, true, false>(I.b4, bi.r0, lds, extra);
+    if (I.bs4 && I.b4.rep_thr)
+      bs4q::bs4_quad<NDIM, true, false, true>(I.b4, bi.r0, lds, extra);
+    else if (I.bs4)
+      bs4q::bs4_quad<NDIM, true, false, false>(I.b4, bi.r0, lds, extra);
     else
       i8q::i8_quad<NDIM, false>(I.i8, bi.r0, lds, lut, extra);
     __syncthreads();

@@ -11,11 +11,11 @@ namespace {
 
 using namespace bs4q;
 
-template <int NDIM, bool FLIPS, bool STATS>
+template <int NDIM, bool FLIPS, bool STATS, bool PT>
 __global__ void __launch_bounds__(kMaxBlock) k_sweep_bs4(Bs4Args a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t extra[kExtraWords];
-  bs4_quad<NDIM, FLIPS, STATS>(a, blockIdx.x * 4, lds, extra);
+  bs4_quad<NDIM, FLIPS, STATS, PT>(a, blockIdx.x * 4, lds, extra);
 }
 
 }  // namespace
@@ -75,12 +75,15 @@ hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStrea
   };
   const bool fl = s.flips != nullptr, st = s.stats != nullptr;
   hipError_t e;
-  if (g->ndim == 2) {
-    if (st) e = fl ? go(k_sweep_bs4<2, true, true>) : go(k_sweep_bs4<2, false, true>);
-    else e = fl ? go(k_sweep_bs4<2, true, false>) : go(k_sweep_bs4<2, false, false>);
+  if (s.rep_thr) {  // replica exchange: no RNG statistics variant
+    if (g->ndim == 2) e = fl ? go(k_sweep_bs4<2, true, false, true>) : go(k_sweep_bs4<2, false, false, true>);
+    else e = fl ? go(k_sweep_bs4<3, true, false, true>) : go(k_sweep_bs4<3, false, false, true>);
+  } else if (g->ndim == 2) {
+    if (st) e = fl ? go(k_sweep_bs4<2, true, true, false>) : go(k_sweep_bs4<2, false, true, false>);
+    else e = fl ? go(k_sweep_bs4<2, true, false, false>) : go(k_sweep_bs4<2, false, false, false>);
   } else {
-    if (st) e = fl ? go(k_sweep_bs4<3, true, true>) : go(k_sweep_bs4<3, false, true>);
-    else e = fl ? go(k_sweep_bs4<3, true, false>) : go(k_sweep_bs4<3, false, false>);
+    if (st) e = fl ? go(k_sweep_bs4<3, true, true, false>) : go(k_sweep_bs4<3, false, true, false>);
+    else e = fl ? go(k_sweep_bs4<3, true, false, false>) : go(k_sweep_bs4<3, false, false, false>);
   }
   if (e != hipSuccess) return e;
   return hipGetLastError();

@@ -60,6 +60,10 @@ def test_replica_thresholds_need_a_four_replica_layout(ising):
         with pytest.raises(ising.IsingError) as e:
             ising.run_trials(g, spins, 1, 10, layout=layout, replica_thresholds=thr)
         assert e.value.code == ising.E_UNSUPPORTED
+    st = torch.zeros(2, dtype=torch.int64, device="cuda")
+    with pytest.raises(ising.IsingError) as e:
+        ising.run_trials(g, spins, 1, 10, replica_thresholds=thr, stats=st)
+    assert e.value.code == ising.E_UNSUPPORTED
     assert ising.select_layout(g, 8) == "bs4"
     g.close()
 
