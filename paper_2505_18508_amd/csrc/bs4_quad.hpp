@@ -145,23 +145,28 @@ __device__ __forceinline__ void quad_thr_finish(QuadThr& th) {
 // The draws of a word's four sites and their compares against the first LEV
 // thresholds: bit 4 j + r of c_k = (Philox word r of site j) < T_k of
 // replica r.  Site j's canonical index: line 4 gl + j, x = 2m + (q ^ (j & 1)).
-template <int LEV>
+// PT: one threshold per replica (th); else one for all four (T1, T2, T3).
+template <int LEV, bool PT>
 __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t Lx, uint32_t q, uint32_t t,
-                                          uint32_t quad, const QuadThr& th, uint32_t& c1, uint32_t& c2,
-                                          uint32_t& c3) {
+                                          uint32_t quad, const QuadThr& th, uint32_t T1, uint32_t T2,
+                                          uint32_t T3, uint32_t& c1, uint32_t& c2, uint32_t& c3) {
 #pragma unroll
   for (int j = 3; j >= 0; --j) {
     const uint32_t ci = ci0 + (uint32_t)j * Lx + (q ^ (uint32_t)(j & 1));
     const u32x4 r = philox_lane_c0(seed, ci, t, quad, kTagMetropolis);
-    lt_shift_in4<LEV>(c1, c2, c3, r.v, th.T[0], th.T[1], th.T[2]);
+    if (PT)
+      lt_shift_in4<LEV>(c1, c2, c3, r.v, th.T[0], th.T[1], th.T[2]);
+    else
+      lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
   }
 }
 
 // One half-sweep of colour P over this thread's words.
-template <int NDIM, int P, bool FLIPS, bool STATS>
+template <int NDIM, int P, bool FLIPS, bool STATS, bool PT>
 __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4Args& a, int t, uint32_t quad,
-                                         const QuadThr& th, uint32_t valid16, uint32_t* fl,
-                                         uint32_t& n_blocks, uint32_t& n_draws) {
+                                         const QuadThr& th, uint32_t T1, uint32_t T2, uint32_t T3,
+                                         uint32_t valid16, uint32_t* fl, uint32_t& n_blocks,
+                                         uint32_t& n_draws) {
   const uint32_t Lx = (uint32_t)a.lat.Lx;
   uint32_t base = wk.base0, ci0 = wk.ci0;
   uint32_t Y = wk.Y0, z = wk.z0;
@@ -181,16 +186,20 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
       k3 = ~(u0 | u1 | u2);
     }
     uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-    if (th.lev != 0) {
+    // compare levels needed: the largest k with a nonzero T_k
+    const bool l1 = PT ? th.lev != 0 : T1 != 0u;
+    const bool only1 = PT ? th.lev == 1 : T2 == 0u;
+    const bool only2 = NDIM == 2 || (PT ? th.lev == 2 : T3 == 0u);
+    if (l1) {
       const uint32_t q = ((uint32_t)P + z) & 1u;
-      if (th.lev == 1)
-        bs4_draws<1>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, c1, c2, c3);
-      else if (NDIM == 2 || th.lev == 2)
-        bs4_draws<2>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, c1, c2, c3);
+      if (only1)
+        bs4_draws<1, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
+      else if (only2)
+        bs4_draws<2, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
       else
-        bs4_draws<3>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, c1, c2, c3);
-      if (STATS) {
-        const uint32_t need = ((k1 & th.m[0]) | (k2 & th.m[1]) | (k3 & th.m[2])) & valid16;
+        bs4_draws<3, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
+      if (STATS) {  // schedule only: per-replica thresholds reject statistics
+        const uint32_t need = (k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & valid16;
         n_blocks += 4u;
         n_draws += __popc(need);
       }
@@ -309,7 +318,7 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   uint32_t fl[4] = {0u, 0u, 0u, 0u};
   uint32_t n_blocks = 0u, n_draws = 0u;  // RNG statistics (STATS only)
 
-  QuadThr th;
+  QuadThr th{};
   if (PT) {  // each replica at its own temperature for the whole window
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -318,26 +327,19 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         th.T[k][b] = (k < NDIM && b < nvalid) ? a.rep_thr[(size_t)(r0 + b) * NDIM + k] : 0u;
     quad_thr_finish(th);
   }
-  // under a schedule the next sweep's thresholds are loaded a sweep ahead,
-  // so no wave waits for them after the barrier
-  uint32_t tn[3] = {0u, 0u, 0u};
-  if (!PT)
-#pragma unroll
-    for (int k = 0; k < NDIM; ++k) tn[k] = a.thr[(size_t)a.t_begin * NDIM + k];
   for (int t = a.t_begin; t < a.t_end; ++t) {
+    uint32_t T1 = 0u, T2 = 0u, T3 = 0u;
     if (!PT) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) th.T[k][b] = tn[k];
-      quad_thr_finish(th);
-      const int tnext = min(t + 1, a.t_end - 1);  // unconditional: no branch to merge
-#pragma unroll
-      for (int k = 0; k < NDIM; ++k) tn[k] = a.thr[(size_t)tnext * NDIM + k];
+      const uint32_t* tr = a.thr + (size_t)t * NDIM;
+      T1 = tr[0];
+      T2 = tr[1];
+      T3 = NDIM == 3 ? tr[2] : 0u;
     }
-    if (active) bs4_half<NDIM, 0, FLIPS, STATS>(lb, wk, a, t, quad, th, valid16, fl, n_blocks, n_draws);
+    if (active)
+      bs4_half<NDIM, 0, FLIPS, STATS, PT>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
     __syncthreads();
-    if (active) bs4_half<NDIM, 1, FLIPS, STATS>(lb, wk, a, t, quad, th, valid16, fl, n_blocks, n_draws);
+    if (active)
+      bs4_half<NDIM, 1, FLIPS, STATS, PT>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
     __syncthreads();
   }
 
