@@ -243,46 +243,65 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
 
   for (int k = tid; k < kExtraWords; k += B) extra[k] = 0u;
 
-  // ---- state and weight masks in, one (colour, word) per step ----------------
+  // ---- state and weight masks in, one record (both colours) per step ----------
+  // Every load of a step is issued before any is used: rows past the last
+  // valid replica repeat that replica's row and are masked out.
   uint32_t bad = 0u;
-  for (uint32_t u = tid; u < 2u * G; u += B) {
-    const uint32_t p = u >= G ? 1u : 0u;
-    const uint32_t g = u - p * G;
+  const size_t row[4] = {(size_t)r0 * n, (size_t)(r0 + min(1, nvalid - 1)) * n,
+                         (size_t)(r0 + min(2, nvalid - 1)) * n, (size_t)(r0 + min(3, nvalid - 1)) * n};
+  for (uint32_t g = tid; g < G; g += B) {
     const uint32_t gl = g / hx, m = g - gl * hx;
     const uint32_t z = gl / LY4;
-    uint32_t word = 0u;
-    uint32_t wm[DEG];
+    uint32_t w0 = 0u, w1 = 0u;  // spin words of colours 0 and 1
+    uint32_t wm0[DEG], wm1[DEG];
 #pragma unroll
-    for (int d = 0; d < DEG; ++d) wm[d] = 0u;
+    for (int d = 0; d < DEG; ++d) wm0[d] = wm1[d] = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t line = 4u * gl + (uint32_t)j;
       const uint32_t y = line - z * Ly;
-      const uint32_t o = (p + y + z) & 1u;
-      const uint32_t ci = line * Lx + 2u * m + o;
-      const uint32_t wb = a.wbits[p * (uint32_t)L.half + line * hx + m];
-      // direction order -> slot order: x-same is +x when o = 0, -x when o = 1
-      const uint32_t ws = o ? ((wb & ~3u) | ((wb & 1u) << 1) | ((wb >> 1) & 1u)) : wb;
+      const uint32_t o0 = (y + z) & 1u;  // colour 0 sits at x = 2m + o0, colour 1 at 2m + 1 - o0
+      const uint32_t cb = line * Lx + 2u * m;
+      const uint32_t wb0 = a.wbits[line * hx + m];
+      const uint32_t wb1 = a.wbits[(uint32_t)L.half + line * hx + m];
+      // direction order -> slot order: x-same is +x at x offset 0, -x at offset 1
+      const uint32_t ws0 = o0 ? ((wb0 & ~3u) | ((wb0 & 1u) << 1) | ((wb0 >> 1) & 1u)) : wb0;
+      const uint32_t ws1 = o0 ? wb1 : ((wb1 & ~3u) | ((wb1 & 1u) << 1) | ((wb1 >> 1) & 1u));
 #pragma unroll
-      for (int d = 0; d < DEG; ++d)
-        if (!((ws >> d) & 1u)) wm[d] |= 0xFu << (4 * j);
+      for (int d = 0; d < DEG; ++d) {
+        if (!((ws0 >> d) & 1u)) wm0[d] |= 0xFu << (4 * j);
+        if (!((ws1 >> d) & 1u)) wm1[d] |= 0xFu << (4 * j);
+      }
       if (a.init) {
-        const u32x4 r = philox_lane_c0(a.seed, ci, 0u, quad, kTagInit);
+        const u32x4 r0v = philox_lane_c0(a.seed, cb + o0, 0u, quad, kTagInit);
+        const u32x4 r1v = philox_lane_c0(a.seed, cb + 1u - o0, 0u, quad, kTagInit);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) word |= (r.v[b] >> 31) << (4 * j + b);
+        for (int b = 0; b < 4; ++b) {
+          w0 |= (r0v.v[b] >> 31) << (4 * j + b);
+          w1 |= (r1v.v[b] >> 31) << (4 * j + b);
+        }
       } else {
-        for (int b = 0; b < nvalid; ++b) {
-          const int8_t v = a.spins[(size_t)(r0 + b) * n + ci];
-          word |= (v > 0 ? 1u : 0u) << (4 * j + b);
-          bad |= (v != 1 && v != -1) ? (1u << b) : 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int8_t ve = a.spins[row[b] + cb], vo = a.spins[row[b] + cb + 1u];  // x = 2m, 2m + 1
+          const uint32_t keep = b < nvalid ? 1u : 0u;
+          const uint32_t ue = ve > 0 ? keep : 0u, uo = vo > 0 ? keep : 0u;
+          w0 |= (o0 ? uo : ue) << (4 * j + b);
+          w1 |= (o0 ? ue : uo) << (4 * j + b);
+          const bool off = (ve != 1 && ve != -1) || (vo != 1 && vo != -1);
+          bad |= (off && keep) ? (1u << b) : 0u;
         }
       }
     }
     uint32_t* rec = lds + g * RS;
-    rec[p] = word;
+    rec[0] = w0;
+    rec[1] = w1;
 #pragma unroll
-    for (int d = 0; d < DEG; ++d) rec[2u + p * DEG + (uint32_t)d] = wm[d];
-    if (p == 0u) rec[RS - 1u] = 0u;  // padding entry
+    for (int d = 0; d < DEG; ++d) {
+      rec[2u + (uint32_t)d] = wm0[d];
+      rec[2u + DEG + (uint32_t)d] = wm1[d];
+    }
+    rec[RS - 1u] = 0u;  // padding entry
   }
   __syncthreads();
   if (bad) atomicOr(&extra[4], bad);
@@ -377,15 +396,26 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   }
   __syncthreads();
 
-  // ---- state out --------------------------------------------------------------
-  for (uint32_t i = tid; i < (uint32_t)L.n; i += B) {
-    const uint32_t line = i / Lx, x = i - line * Lx;
-    const uint32_t z = line / Ly, y = line - z * Ly;
-    const uint32_t p = (x + y + z) & 1u;
-    const uint32_t word = lds[((line >> 2) * hx + (x >> 1)) * RS + p];
-    const uint32_t j = line & 3u;
-    for (int b = 0; b < nvalid; ++b)
-      a.spins[(size_t)(r0 + b) * n + i] = ((word >> (4u * j + (uint32_t)b)) & 1u) ? (int8_t)1 : (int8_t)-1;
+  // ---- state out, one record (both colours) per step ----------------------------
+  for (uint32_t g = tid; g < G; g += B) {
+    const uint32_t gl = g / hx, m = g - gl * hx;
+    const uint32_t z = gl / LY4;
+    const uint32_t w0 = lds[g * RS], w1 = lds[g * RS + 1u];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t line = 4u * gl + (uint32_t)j;
+      const uint32_t o0 = (line - z * Ly + z) & 1u;
+      const uint32_t cb = line * Lx + 2u * m;
+      const uint32_t we = o0 ? w1 : w0, wo = o0 ? w0 : w1;  // words holding x = 2m and 2m + 1
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (b < nvalid) {
+          const uint32_t sh = 4u * (uint32_t)j + (uint32_t)b;
+          a.spins[row[b] + cb] = ((we >> sh) & 1u) ? (int8_t)1 : (int8_t)-1;
+          a.spins[row[b] + cb + 1u] = ((wo >> sh) & 1u) ? (int8_t)1 : (int8_t)-1;
+        }
+      }
+    }
   }
   const int64_t n_edges = (int64_t)NDIM * L.n;
   for (int b = tid; b < nvalid; b += B) {

@@ -251,24 +251,48 @@ __device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t*
   for (int k = tid; k < kExtraWords; k += B) extra[k] = 0u;
 
   // ---- state in: spin bits in colour-split order --------------------------
+  // Two sites per step and every replica row loaded before any is used: rows
+  // past the last valid replica repeat that replica's row and are masked out.
   uint32_t bad = 0u;
-  for (uint32_t i = tid; i < (uint32_t)L.n; i += B) {
-    int p;
-    uint32_t h;
-    site_to_split(L, i, p, h);
-    uint32_t word = 0u;
+  const size_t row[4] = {(size_t)r0 * n, (size_t)(r0 + min(1, nvalid - 1)) * n,
+                         (size_t)(r0 + min(2, nvalid - 1)) * n, (size_t)(r0 + min(3, nvalid - 1)) * n};
+  const uint32_t nn = (uint32_t)L.n;
+  for (uint32_t i0 = tid; i0 < nn; i0 += 2u * (uint32_t)B) {
+    const uint32_t i1 = i0 + (uint32_t)B;
+    const bool has1 = i1 < nn;
+    const uint32_t ii[2] = {i0, has1 ? i1 : i0};
+    uint32_t word[2] = {0u, 0u};
     if (a.init) {
-      const u32x4 u = philox_lane_c0(a.seed, i, 0u, quad, kTagInit);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) word |= (u.v[b] >> 31) << (8 * b + kSpinBit);
+      for (int e = 0; e < 2; ++e) {
+        const u32x4 u = philox_lane_c0(a.seed, ii[e], 0u, quad, kTagInit);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word[e] |= (u.v[b] >> 31) << (8 * b + kSpinBit);
+      }
     } else {
-      for (int b = 0; b < nvalid; ++b) {
-        const int8_t v = a.spins[(size_t)(r0 + b) * n + i];
-        word |= (v > 0 ? 1u : 0u) << (8 * b + kSpinBit);
-        bad |= (v != 1 && v != -1) ? (1u << b) : 0u;
+      int8_t v[2][4];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[e][b] = a.spins[row[b] + ii[e]];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const bool keep = b < nvalid;
+          word[e] |= (keep && v[e][b] > 0 ? 1u : 0u) << (8 * b + kSpinBit);
+          bad |= (keep && v[e][b] != 1 && v[e][b] != -1) ? (1u << b) : 0u;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (e == 0 || has1) {
+        int p;
+        uint32_t h;
+        site_to_split(L, ii[e], p, h);
+        lds[(uint32_t)p * (uint32_t)L.half + h] = word[e];
       }
     }
-    lds[(uint32_t)p * (uint32_t)L.half + h] = word;
   }
   __syncthreads();
   if (bad) atomicOr(&extra[4], bad);
@@ -428,8 +452,9 @@ __device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t*
     uint32_t h;
     site_to_split(L, i, p, h);
     const uint32_t word = lds[(uint32_t)p * (uint32_t)L.half + h];
-    for (int b = 0; b < nvalid; ++b)
-      a.spins[(size_t)(r0 + b) * n + i] = ((word >> (8 * b + kSpinBit)) & 1u) ? (int8_t)1 : (int8_t)-1;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b < nvalid) a.spins[row[b] + i] = ((word >> (8 * b + kSpinBit)) & 1u) ? (int8_t)1 : (int8_t)-1;
   }
   for (int b = tid; b < nvalid; b += B) {
     const int r = r0 + b;
