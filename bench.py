@@ -25,31 +25,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "c2": dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05, beta1=4.0,
+    "torus100x100": dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05, beta1=4.0,
                name="2-D torus 100x100 (10,000 spins, weight seed 2), 1,024 replicas, 10,000 sweeps, "
                     "geometric beta 0.05->4.0, run seed 102"),
-    "c4": dict(dims=[100, 200], weight_seed=81, seed=201, R=8192, S=40000, schedule="geometric", beta0=0.05, beta1=4.0,
+    "torus100x200": dict(dims=[100, 200], weight_seed=81, seed=201, R=8192, S=40000, schedule="geometric", beta0=0.05, beta1=4.0,
                name="2-D torus 100x200 (20,000 spins, weight seed 81), 8,192 replicas, 40,000 sweeps, "
                     "geometric beta 0.05->4.0, run seed 201"),
 }
-WORKLOADS["c3"] = dict(
+WORKLOADS["batch4tori"] = dict(
     instances=[([50, 100], 11, 111, 256, 5000), ([100, 100], 12, 112, 1024, 10000), ([100, 140], 13, 113, 2048, 15000),
                ([100, 200], 14, 114, 4096, 20000)],
     schedule="geometric", beta0=0.05, beta1=4.0,
     name="batch of 2-D tori 50x100 / 100x100 / 100x140 / 100x200 (weight seeds 11-14) with 256 / 1,024 / 2,048 / "
          "4,096 replicas and 5,000 / 10,000 / 15,000 / 20,000 sweeps in one persistent launch, geometric beta "
          "0.05->4.0, run seeds 111-114")
-WORKLOADS["c5"] = dict(dims=[1000, 1000], weight_seed=1000, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
+WORKLOADS["torus1000x1000"] = dict(dims=[1000, 1000], weight_seed=1000, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
                        beta1=4.0, name="2-D torus 1000x1000 (1,000,000 spins, weight seed 1000), 256 replicas, 2,000 "
                                         "sweeps streamed from HBM, geometric beta 0.05->4.0, run seed 7")
-WORKLOADS["c5_3d"] = dict(dims=[64, 64, 64], weight_seed=643, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
+WORKLOADS["torus64x64x64"] = dict(dims=[64, 64, 64], weight_seed=643, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
                           beta1=4.0, name="3-D torus 64^3 (262,144 spins, degree 6, weight seed 643), 256 replicas, "
                                           "2,000 sweeps streamed from HBM, geometric beta 0.05->4.0, run seed 7")
 HBM_PEAK = 8e12
 # streamed layout: per sweep each 32-replica word is read and written once and
 # its neighbours' words read once: 12 bytes per word per sweep
 STREAM_BYTES_PER_WORD_SWEEP = 12
-WORKLOAD = WORKLOADS["c2"]
+WORKLOAD = WORKLOADS["torus100x100"]
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU issue
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # algorithmic VALU lane-ops: one Philox4x32-10 word per attempt that needs a
@@ -175,7 +175,7 @@ def bench_batch(args, ising, metrics, torch, dev):
         "kernel_attempts_per_s": attempts / kernel_s, "kernel_ms": kernel_s * 1e3,
         "roofline": {"bound": "alu", "achieved": ops / kernel_s / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": ops / kernel_s / VALU_PEAK_LANE_OPS,
-                     "traffic": measured_traffic("k_sweep_batch", "c3"), "kernel": "k_sweep_batch",
+                     "traffic": measured_traffic("k_sweep_batch", "batch4tori"), "kernel": "k_sweep_batch",
                      "draws": draws, "draw_fraction": draws / attempts},
         "readout": {"best_cut_per_instance": bests},
     }
@@ -192,13 +192,13 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="torus100x100")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a reference kernel of known traffic for counters)")
     args = ap.parse_args()
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]
-    if args.workload in ("c3", "c5", "c5_3d"):
+    if args.workload in ("batch4tori", "torus1000x1000", "torus64x64x64"):
         args.no_cpu = True  # the oracle baseline is measured on the single-instance on-chip workloads
     if args.gpus != 1:
         print("bench.py measures one GPU only: the replica-parallel path has no cross-GPU step to time "
@@ -224,7 +224,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     W = WORKLOAD
-    if args.workload == "c3":
+    if args.workload == "batch4tori":
         print(json.dumps(bench_batch(args, ising, metrics, torch, dev)))
         return
     g = ising.create_graph(W["dims"], W["weight_seed"])

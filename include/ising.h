@@ -55,7 +55,7 @@ enum {
   ISING_E_TOPOLOGY = -2,     /* torus shape not supported (odd or < 2 dimension)    */
   ISING_E_NOMEM = -3,        /* host or device allocation failed                    */
   ISING_E_HIP = -4,          /* HIP runtime error (includes errors of earlier work) */
-  ISING_E_UNSUPPORTED = -5,  /* valid request this build cannot run (e.g. too large)*/
+  ISING_E_UNSUPPORTED = -5,  /* valid request the library cannot run (e.g. too large) */
   ISING_E_STATE = -6         /* object in the wrong state for the call              */
 };
 
@@ -288,7 +288,7 @@ void ising_batch_destroy(ising_batch* b);
  * that unpromising replicas are replaced by copies of promising ones.  (The
  * paper's trials are independent runs read out at their end, Section III;
  * culling is this library's extension of that campaign, and the plain
- * all-trials run remains the reference it is judged against with eq. (3).)
+ * all-trials run remains the reference it is compared with by eq. (3).)
  * ---------------------------------------------------------------------- */
 
 #define ISING_N_FEATURES 16

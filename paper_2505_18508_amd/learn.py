@@ -8,7 +8,7 @@ current cut plus predicted gain); the score ranks the replicas, and the
 lower half is replaced by copies of the upper half.  Every
 replica keeps its own Philox stream, so copies diverge at once.  The plain
 form (no culling) runs the same windows and is what the learned form is
-judged against, with eq. (3)-(5) applied to both.
+compared with, eq. (3)-(5) applied to both.
 
 All arithmetic runs in the library's HIP kernels; this module sequences
 them on one stream and holds the buffers (torch device tensors).
