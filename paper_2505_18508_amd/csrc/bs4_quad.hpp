@@ -171,6 +171,10 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
   uint32_t base = wk.base0, ci0 = wk.ci0;
   uint32_t Y = wk.Y0, z = wk.z0;
   for (uint32_t gl = wk.gl0; gl < wk.GL; gl += wk.lp) {
+    if (NDIM == 2) {  // one plane: the word line is the row, z = 0
+      Y = gl;
+      z = 0u;
+    }
     uint32_t s, u0, u1, u2;
     bs4_bonds<NDIM, P>(lds, base, wk, Y, z, s, u0, u1, u2);
     // dE = 2 deg - 4u: flip when u >= deg/2; else k = deg/2 - u
@@ -212,11 +216,13 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
     }
     base += wk.step;
     ci0 += wk.ci_step;
-    Y += wk.lp_y;
-    z += wk.lp_z;
-    if (Y >= wk.LY4) {
-      Y -= wk.LY4;
-      z += 1u;
+    if (NDIM == 3) {
+      Y += wk.lp_y;
+      z += wk.lp_z;
+      if (Y >= wk.LY4) {
+        Y -= wk.LY4;
+        z += 1u;
+      }
     }
   }
 }
@@ -368,6 +374,10 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
     uint32_t base = wk.base0;
     uint32_t Y = wk.Y0, z = wk.z0;
     for (uint32_t gl = gl0; gl < GL; gl += lp) {
+      if (NDIM == 2) {
+        Y = gl;
+        z = 0u;
+      }
       uint32_t s, u0, u1, u2;
       bs4_bonds<NDIM, 0>(lb, base, wk, Y, z, s, u0, u1, u2);
 #pragma unroll
@@ -376,11 +386,13 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         e[b] += __popc(u0 & mr) + 2u * __popc(u1 & mr) + 4u * __popc(u2 & mr);
       }
       base += wk.step;
-      Y += wk.lp_y;
-      z += wk.lp_z;
-      if (Y >= LY4) {
-        Y -= LY4;
-        z += 1u;
+      if (NDIM == 3) {
+        Y += wk.lp_y;
+        z += wk.lp_z;
+        if (Y >= LY4) {
+          Y -= LY4;
+          z += 1u;
+        }
       }
     }
 #pragma unroll
