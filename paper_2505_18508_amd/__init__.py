@@ -142,6 +142,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _dev(t, name, dtypes, numel=None):
+    """_ptr after checking that t has one of dtypes (torch dtype names) and at
+    least numel elements: the kernels index these buffers by the sizes the
+    call states, so a short or mistyped buffer is refused here."""
+    if t is None:
+        return None
+    import torch
+
+    if t.dtype not in tuple(getattr(torch, d) for d in dtypes):
+        raise ValueError("%s must be %s, got %s" % (name, " or ".join(dtypes), str(t.dtype).replace("torch.", "")))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    return _ptr(t)
+
+
+I32 = ("int32", "uint32")
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -226,8 +244,9 @@ def make_params(seed, n_replicas, n_sweeps, sweep_begin=0, sweep_end=None, sched
         p.beta_table = keep.ctypes.data
     p.block_threads = int(block_threads)
     p.replica_offset = int(replica_offset)
-    p.stats_out = None if stats is None else _ptr(stats).value
-    p.replica_thresholds = None if replica_thresholds is None else _ptr(replica_thresholds).value
+    p.stats_out = None if stats is None else _dev(stats, "stats", ("int64",), 2).value
+    p.replica_thresholds = None if replica_thresholds is None else _dev(
+        replica_thresholds, "replica_thresholds", I32).value
     return p, keep
 
 
@@ -253,15 +272,18 @@ def run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, sche
         raise ValueError("replica_thresholds must be [R][%d]" % (graph.degree // 2))
     p, keep = make_params(seed, R, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1, beta_table,
                           init_spins, layout, block_threads, replica_offset, stats, replica_thresholds)
-    _check(lib().ising_run_trials(graph.handle, ctypes.byref(p), _ptr(spins), _ptr(cut), _ptr(energy), _ptr(flips),
-                                  _stream(stream)))
+    _check(lib().ising_run_trials(graph.handle, ctypes.byref(p), _dev(spins, "spins", ("int8",)),
+                                  _dev(cut, "cut", ("int64",), R), _dev(energy, "energy", ("int64",), R),
+                                  _dev(flips, "flips", I32, R), _stream(stream)))
     del keep
 
 
 def eval_cut(graph, spins, cut=None, energy=None, stream=None):
     if spins.dim() != 2 or spins.shape[1] != graph.n:
         raise ValueError("spins must be [R][%d]" % graph.n)
-    _check(lib().ising_eval_cut(graph.handle, _ptr(spins), spins.shape[0], _ptr(cut), _ptr(energy), _stream(stream)))
+    R = spins.shape[0]
+    _check(lib().ising_eval_cut(graph.handle, _dev(spins, "spins", ("int8",)), R, _dev(cut, "cut", ("int64",), R),
+                                _dev(energy, "energy", ("int64",), R), _stream(stream)))
 
 
 def thresholds(n_sweeps, schedule="linear", beta0=0.1, beta1=3.0, beta_table=None, degree=4):
@@ -284,7 +306,11 @@ def schedule_beta(n_sweeps, t, schedule="linear", beta0=0.1, beta1=3.0, beta_tab
 
 def philox_dump(key, ctr, out, stream=None):
     """Philox4x32-10 blocks on the GPU: ctr, out uint32/int32 device [m][4]."""
-    _check(lib().ising_philox_dump(int(key), _ptr(ctr), ctr.shape[0], _ptr(out), _stream(stream)))
+    m = ctr.shape[0]
+    if ctr.dim() != 2 or ctr.shape[1] != 4:
+        raise ValueError("ctr must be [m][4]")
+    _check(lib().ising_philox_dump(int(key), _dev(ctr, "ctr", I32), m, _dev(out, "out", I32, 4 * m),
+                                   _stream(stream)))
 
 
 # ---------------------------------------------------------------------------
@@ -301,9 +327,13 @@ def features(graph, spins, energy, window_flips, track, sweeps_done, window, n_s
              stream=None):
     """ising_features: out float32 [R][16]; track updated in place."""
     R = spins.shape[0]
-    _check(lib().ising_features(graph.handle, _ptr(spins), _ptr(energy), _ptr(window_flips), R, _ptr(track),
-                                int(sweeps_done), int(window), int(n_sweeps), float(beta), int(n_checkpoints),
-                                _ptr(out), _stream(stream)))
+    if spins.dim() != 2 or spins.shape[1] != graph.n:
+        raise ValueError("spins must be [R][%d]" % graph.n)
+    _check(lib().ising_features(graph.handle, _dev(spins, "spins", ("int8",)), _dev(energy, "energy", ("int64",), R),
+                                _dev(window_flips, "window_flips", I32, R),
+                                R, _dev(track, "track", ("int64",), R * TRACK_WORDS), int(sweeps_done), int(window),
+                                int(n_sweeps), float(beta), int(n_checkpoints),
+                                _dev(out, "features", ("float32",), R * N_FEATURES), _stream(stream)))
 
 
 def mlp_init(seed, params, stream=None):
@@ -339,17 +369,23 @@ def feature_stats(x, mean, std, rows=None, stream=None):
 
 def cull_clone(score, spins, track=None, order=None, stream=None):
     R, n = spins.shape
-    _check(lib().ising_cull_clone(_ptr(score), R, n, _ptr(spins), _ptr(track), _ptr(order), _stream(stream)))
+    _check(lib().ising_cull_clone(_dev(score, "score", ("float32",), R), R, n, _dev(spins, "spins", ("int8",)),
+                                  _dev(track, "track", ("int64",), R * TRACK_WORDS), _dev(order, "order", I32, R),
+                                  _stream(stream)))
 
 
 def final_cut_score(graph, gain, feats, score, stream=None):
     """score = predicted final cut / |E| from the network's gain prediction."""
-    _check(lib().ising_final_cut_score(graph.handle, _ptr(gain), _ptr(feats), gain.shape[0], _ptr(score),
-                                       _stream(stream)))
+    R = gain.shape[0]
+    _check(lib().ising_final_cut_score(graph.handle, _dev(gain, "gain", ("float32",)),
+                                       _dev(feats, "features", ("float32",), R * N_FEATURES), R,
+                                       _dev(score, "score", ("float32",), R), _stream(stream)))
 
 
 def energy_score(energy, score, stream=None):
-    _check(lib().ising_energy_score(_ptr(energy), energy.shape[0], _ptr(score), _stream(stream)))
+    R = energy.shape[0]
+    _check(lib().ising_energy_score(_dev(energy, "energy", ("int64",)), R, _dev(score, "score", ("float32",), R),
+                                    _stream(stream)))
 
 
 # ---------------------------------------------------------------------------
@@ -378,9 +414,11 @@ class Batch:
                                   run.get("layout", "auto"), 0, run.get("replica_offset", 0))
             params[i] = p
             self._keep.append(keep)
+            R = spins.shape[0]
+            kinds = {"spins": (("int8",), None), "cut": (("int64",), R), "energy": (("int64",), R), "flips": (I32, R)}
             for name in ptrs:
                 t = run.get(name)
-                ptrs[name][i] = None if t is None else _ptr(t).value
+                ptrs[name][i] = None if t is None else _dev(t, name, *kinds[name]).value
         h = ctypes.c_void_p()
         _check(lib().ising_batch_create(k, gh, params, ptrs["spins"], ptrs["cut"], ptrs["energy"], ptrs["flips"],
                                         ctypes.byref(h)))
@@ -422,8 +460,10 @@ class PT:
             stream=None):
         if spins.dim() != 2 or spins.shape != (self.n_replicas, self.graph.n):
             raise ValueError("spins must be [%d][%d]" % (self.n_replicas, self.graph.n))
-        _check(lib().ising_pt_run(self._h, _ptr(spins), 1 if init_spins else 0, int(round_begin), int(n_rounds),
-                                  int(sweeps_per_round), _ptr(cut), _ptr(energy), _stream(stream)))
+        R = self.n_replicas
+        _check(lib().ising_pt_run(self._h, _dev(spins, "spins", ("int8",)), 1 if init_spins else 0, int(round_begin),
+                                  int(n_rounds), int(sweeps_per_round), _dev(cut, "cut", ("int64",), R),
+                                  _dev(energy, "energy", ("int64",), R), _stream(stream)))
 
     def labels(self, out=None, stream=None):
         """Temperature index of every slot (device int32 [L K])."""
@@ -431,7 +471,7 @@ class PT:
 
         if out is None:
             out = torch.zeros(self.n_replicas, dtype=torch.int32, device="cuda")
-        _check(lib().ising_pt_state(self._h, _ptr(out), None, _stream(stream)))
+        _check(lib().ising_pt_state(self._h, _dev(out, "out", I32, self.n_replicas), None, _stream(stream)))
         return out
 
     def accepted(self):

@@ -427,6 +427,8 @@ int ising_features(const ising_graph* g, const int8_t* spins, const int64_t* ene
   if (window < 1 || sweeps_done < window || n_sweeps < sweeps_done || n_checkpoints < 1)
     return fail(ISING_E_ARG, "need 1 <= window <= sweeps_done <= n_sweeps and n_checkpoints >= 1");
   if (!(beta > 0.0) || !std::isfinite(beta)) return fail(ISING_E_ARG, "beta must be finite and > 0");
+  const int rc = ising::check_device(g);  // the kernel reads the graph's device weights
+  if (rc) return rc;
   ising::FeatArgs a;
   a.lat = g->lat;
   a.w = g->d_w;

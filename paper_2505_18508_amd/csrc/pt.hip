@@ -211,6 +211,8 @@ int ising_pt_run(ising_pt* pt, int8_t* spins, int32_t init_spins, int32_t round_
   if (init_spins && round_begin != 0) return fail(ISING_E_ARG, "init_spins needs round_begin == 0");
   if ((int64_t)(round_begin + (int64_t)n_rounds) * sweeps_per_round > INT32_MAX)
     return fail(ISING_E_ARG, "sweep indices exceed 2^31 - 1");
+  int rc = check_device(pt->g);
+  if (rc) return rc;
   if (n_rounds == 0) return ISING_OK;
   hipStream_t st = (hipStream_t)stream;
   const int32_t end_round = round_begin + n_rounds;
@@ -227,7 +229,7 @@ int ising_pt_run(ising_pt* pt, int8_t* spins, int32_t init_spins, int32_t round_
     p.beta0 = p.beta1 = 0.0;  // unused: per-replica thresholds
     p.init_spins = (init_spins && q == 0) ? 1 : 0;
     p.replica_thresholds = pt->d_rep_thr;
-    int rc = ising_run_trials(pt->g, &p, spins, q + 1 == end_round ? cut_out : nullptr, pt->d_energy, nullptr, st);
+    rc = ising_run_trials(pt->g, &p, spins, q + 1 == end_round ? cut_out : nullptr, pt->d_energy, nullptr, st);
     if (rc) return rc;
     const int32_t npairs = (pt->K - (q & 1)) / 2;
     const int64_t threads = (int64_t)pt->L * npairs;
@@ -248,6 +250,8 @@ int ising_pt_run(ising_pt* pt, int8_t* spins, int32_t init_spins, int32_t round_
 int ising_pt_state(const ising_pt* pt, int32_t* temp_index_out, uint64_t* accepted_out, void* stream) {
   using namespace ising;
   if (!pt) return fail(ISING_E_ARG, "handle is NULL");
+  int rc = check_device(pt->g);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if (temp_index_out)
     hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)((pt->R + 255) / 256)), dim3(256), 0, st,

@@ -284,6 +284,15 @@ def test_argument_errors(dev):
         with pytest.raises(ising.IsingError) as e:
             ising.run_trials(g, s, 1, n_sweeps, **kw)
         assert e.value.code == ising.E_ARG, kw
+    # short or mistyped output buffers never reach a kernel
+    short = torch.zeros(3, dtype=torch.int64, device="cuda")
+    for kw in (dict(cut=short), dict(energy=short), dict(flips=torch.zeros(4, dtype=torch.int64, device="cuda"))):
+        with pytest.raises(ValueError):
+            ising.run_trials(g, s, 1, 10, **kw)
+    with pytest.raises(ValueError):
+        ising.eval_cut(g, s, short, None)
+    with pytest.raises(ValueError):
+        ising.run_trials(g, s.to(torch.int32), 1, 10)
 
 
 # --------------------------------------------------------------------------

@@ -105,3 +105,21 @@ def test_one_hip_runtime_in_the_process():
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_binding_refuses_mistyped_or_short_buffers():
+    """The binding checks dtype and length of every sized buffer before any
+    pointer reaches the library (host tensors: no device is needed)."""
+    import torch
+
+    import paper_2505_18508_amd as ising
+
+    with pytest.raises(ValueError, match="must be int64"):
+        ising._dev(torch.zeros(4, dtype=torch.int32), "cut", ("int64",), 4)
+    with pytest.raises(ValueError, match="holds 3 elements, needs 4"):
+        ising._dev(torch.zeros(3, dtype=torch.int64), "cut", ("int64",), 4)
+    with pytest.raises(ValueError, match="device tensor"):
+        ising._dev(torch.zeros(4, dtype=torch.int64), "cut", ("int64",), 4)
+    with pytest.raises(ValueError, match="must be int32 or uint32"):
+        ising._dev(torch.zeros(4, dtype=torch.float32), "flips", ising.I32, 4)
+    assert ising._dev(None, "cut", ("int64",), 4) is None
