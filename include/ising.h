@@ -366,6 +366,15 @@ int ising_adam_step(float* params, const float* grad, float* m, float* v, int64_
  * order; mean, std: device float [16].  Asynchronous. */
 int ising_feature_stats(const float* x, int64_t rows, float* mean, float* std, void* stream);
 
+/* In place, for every group g and column c of a device float
+ * [n_groups][rows][cols] table: x = (x - mean) / std with the mean and
+ * population standard deviation (floored at 1e-6) of column c over the rows
+ * of group g, computed in double in a fixed order (two passes) and rounded
+ * to float once.  A group is one population compared at one checkpoint (the
+ * replicas of a run): what the whole group shares becomes 0, what remains
+ * is each row's standing within it.  rows >= 1, cols >= 1.  Asynchronous. */
+int ising_standardize_groups(float* x, int64_t n_groups, int64_t rows, int32_t cols, void* stream);
+
 /*
  * Rank R replicas by score (higher first; ties: lower index first; NaN
  * last) and let the bottom floor(R/2) take copies of the top floor(R/2):

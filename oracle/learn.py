@@ -56,6 +56,17 @@ def normalise(x, mean=None, std=None):
     return (x - np.asarray(mean, np.float64)) / np.asarray(std, np.float64)
 
 
+def standardize_groups(x, n_groups, rows, cols):
+    """Per group and column: (x - mean) / std over the group's rows, with the
+    population standard deviation floored at 1e-6, in float64, returned as
+    float32 (the standing of each row within its population)."""
+    a = np.asarray(x, np.float64).reshape(n_groups, rows, cols)
+    mu = a.mean(axis=1, keepdims=True)
+    sd = np.sqrt(((a - mu) ** 2).mean(axis=1, keepdims=True))
+    sd = np.maximum(sd, 1e-6)
+    return ((a - mu) / sd).astype(np.float32).reshape(np.shape(x))
+
+
 def forward(theta, z):
     """Network output for inputs z [B][16] (already normalised)."""
     p = unpack(theta)

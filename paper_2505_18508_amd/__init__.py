@@ -32,7 +32,7 @@ EXPORTED = [
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
     "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy", "ising_final_cut_score",
-    "ising_pt_create", "ising_pt_run", "ising_pt_state", "ising_pt_destroy",
+    "ising_pt_create", "ising_pt_run", "ising_pt_state", "ising_pt_destroy", "ising_standardize_groups",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -115,6 +115,7 @@ def lib():
         L.ising_pt_create.argtypes = [vp, i32, vp, i32, u64, ctypes.POINTER(vp)]
         L.ising_pt_run.argtypes = [vp, vp, i32, i32, i32, i32, vp, vp, vp]
         L.ising_pt_state.argtypes = [vp, vp, vp, vp]
+        L.ising_standardize_groups.argtypes = [vp, i64, i64, i32, vp]
         L.ising_pt_destroy.argtypes = [vp]
         L.ising_pt_destroy.restype = None
         for name in EXPORTED:
@@ -380,6 +381,13 @@ def final_cut_score(graph, gain, feats, score, stream=None):
     _check(lib().ising_final_cut_score(graph.handle, _dev(gain, "gain", ("float32",)),
                                        _dev(feats, "features", ("float32",), R * N_FEATURES), R,
                                        _dev(score, "score", ("float32",), R), _stream(stream)))
+
+
+def standardize_groups(x, n_groups, rows, cols, stream=None):
+    """In place: every column of every group of rows of a float32 [n_groups][rows][cols]
+    table to zero mean and unit (population) deviation within the group."""
+    _check(lib().ising_standardize_groups(_dev(x, "x", ("float32",), int(n_groups) * int(rows) * int(cols)),
+                                          int(n_groups), int(rows), int(cols), _stream(stream)))
 
 
 def energy_score(energy, score, stream=None):

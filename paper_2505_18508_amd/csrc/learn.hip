@@ -332,6 +332,40 @@ __global__ void __launch_bounds__(kStatBlock) k_colstats_partial(const float* x,
   }
 }
 
+// One block per (group, column): mean, then the sum of squared deviations,
+// each reduced in double by a fixed tree, then the standardised column.
+constexpr int kStdBlock = 256;
+__global__ void __launch_bounds__(kStdBlock) k_standardize(float* x, int64_t rows, int32_t cols) {
+  __shared__ double red[kStdBlock];
+  const int64_t g = blockIdx.x / (uint32_t)cols;
+  const int32_t c = (int32_t)(blockIdx.x - g * cols);
+  float* base = x + (size_t)g * (size_t)rows * (size_t)cols + c;
+  const int tid = threadIdx.x;
+  auto block_sum = [&](double v) {
+    red[tid] = v;
+    __syncthreads();
+    for (int h = kStdBlock / 2; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+  };
+  double s = 0.0;
+  for (int64_t r = tid; r < rows; r += kStdBlock) s += (double)base[(size_t)r * cols];
+  const double mu = block_sum(s) / (double)rows;
+  double q = 0.0;
+  for (int64_t r = tid; r < rows; r += kStdBlock) {
+    const double d = (double)base[(size_t)r * cols] - mu;
+    q += d * d;
+  }
+  double sd = sqrt(block_sum(q) / (double)rows);
+  if (sd < 1e-6) sd = 1e-6;
+  for (int64_t r = tid; r < rows; r += kStdBlock)
+    base[(size_t)r * cols] = (float)(((double)base[(size_t)r * cols] - mu) / sd);
+}
+
 __global__ void k_colstats_final(const double* part, int64_t rows, float* mean, float* sd) {
   const int c = threadIdx.x;
   if (c >= NF) return;
@@ -524,6 +558,17 @@ int ising_feature_stats(const float* x, int64_t rows, float* mean, float* std, v
   e = hipGetLastError();
   (void)hipFreeAsync(part, st);
   return e == hipSuccess ? ISING_OK : fail_hip(e, "feature stats launch");
+}
+
+int ising_standardize_groups(float* x, int64_t n_groups, int64_t rows, int32_t cols, void* stream) {
+  if (n_groups < 0 || rows < 1 || cols < 1) return fail(ISING_E_ARG, "need n_groups >= 0, rows >= 1, cols >= 1");
+  if (n_groups * (int64_t)cols > (int64_t)INT32_MAX) return fail(ISING_E_UNSUPPORTED, "too many groups x columns");
+  if (n_groups == 0) return ISING_OK;
+  if (!x) return fail(ISING_E_ARG, "NULL buffer");
+  hipLaunchKernelGGL(ising::k_standardize, dim3((unsigned)(n_groups * cols)), dim3(ising::kStdBlock), 0,
+                     (hipStream_t)stream, x, rows, cols);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ISING_OK : fail_hip(e, "standardize launch");
 }
 
 int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, int8_t* spins, ising_track* track,

@@ -4,7 +4,9 @@ A trial (paper, Section III) is a run of S sweeps read out at its end.  Here
 R trials run together and, every `window` sweeps, each replica's trajectory
 features go through a small network that predicts its end-of-trial cut
 (label "final"), or the cut it will still gain (label "gain", scored as
-current cut plus predicted gain); the score ranks the replicas, and the
+current cut plus predicted gain), or its end-of-trial cut's standing among
+the run's replicas from features standardised within the checkpoint's
+population (label "relative"); the score ranks the replicas, and the
 lower half is replaced by copies of the upper half.  Every
 replica keeps its own Philox stream, so copies diverge at once.  The plain
 form (no culling) runs the same windows and is what the learned form is
@@ -19,19 +21,23 @@ import time
 import numpy as np
 
 from . import (adam_step, create_graph, cull_clone, energy_score, feature_stats, features, final_cut_score,
-               mlp_forward, mlp_init, mlp_loss_grad, mlp_workspace_floats, new_track, run_trials, schedule_beta)
+               mlp_forward, mlp_init, mlp_loss_grad, mlp_workspace_floats, new_track, run_trials, schedule_beta,
+               standardize_groups)
 from . import metrics
 
 METHODS = ("plain", "learned", "energy")
 
 
-LABELS = ("final", "gain")
+LABELS = ("final", "gain", "relative")
 
 
 class Model:
     """Network parameters, the feature normalisation they were trained with,
     and what the output means: "final" = end-of-trial cut / |E|; "gain" = cut
-    still to come / |E| (the score adds the current cut back)."""
+    still to come / |E| (the score adds the current cut back); "relative" =
+    end-of-trial cut standardised over the run's replicas, read from features
+    standardised over the replicas at the same checkpoint (mean 0, std 1
+    then stand for no further normalisation)."""
 
     def __init__(self, params, mean, std, label="final"):
         if label not in LABELS:
@@ -102,6 +108,8 @@ def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, 
                     on_checkpoint(k, end, feats)
             if method != "plain":
                 if method == "learned":
+                    if model.label == "relative":  # each replica's standing at this checkpoint
+                        standardize_groups(feats, 1, R, 16, stream=st)
                     mlp_forward(model.params, feats, score, mean=model.mean, std=model.std, stream=st)
                     if model.label == "gain":
                         final_cut_score(graph, score, feats, score, stream=st)
@@ -119,24 +127,35 @@ def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, 
 def trajectories(instances, n_replicas, n_sweeps, window, schedule="geometric", beta0=0.05, beta1=4.0,
                  layout="auto", label="final"):
     """Training rows from plain runs: features at every checkpoint, labelled
-    with the end-of-trial cut / |E| (label "final") or with the cut still to
-    come, (final cut - cut at the checkpoint) / |E| (label "gain").
+    with the end-of-trial cut / |E| (label "final"), with the cut still to
+    come, (final cut - cut at the checkpoint) / |E| (label "gain"), or with
+    the end-of-trial cut standardised over the run's replicas, the features
+    standardised over the replicas of their checkpoint (label "relative").
     instances: [(dims, weight_seed, run_seed)].  Returns device tensors
-    X [N][16], Y [N]."""
+    X [N][16], Y [N] (instance-major, then checkpoint, then replica)."""
     import torch
 
     xs, ys = [], []
+    R = n_replicas
     for dims, wseed, rseed in instances:
         g = create_graph(dims, wseed)
         rows, cuts = [], {}
-        out = anneal(g, n_replicas, n_sweeps, rseed, schedule, beta0, beta1, window, "plain", layout=layout,
+        out = anneal(g, R, n_sweeps, rseed, schedule, beta0, beta1, window, "plain", layout=layout,
                      on_checkpoint=lambda k, e, f: rows.append(f.clone()),
                      on_window=lambda k, e, c: cuts.__setitem__(k, c.clone()))
         final = out["cut"]
-        xs.extend(rows)
-        for k in range(len(rows)):
-            y = final - cuts[k] if label == "gain" else final
-            ys.append(y.to(torch.float32) / float(g.n_edges))
+        if label == "relative":
+            X = torch.cat(rows)
+            standardize_groups(X, len(rows), R, 16)
+            y = final.to(torch.float32)
+            standardize_groups(y, 1, R, 1)
+            xs.append(X)
+            ys.extend([y] * len(rows))
+        else:
+            xs.extend(rows)
+            for k in range(len(rows)):
+                y = final - cuts[k] if label == "gain" else final
+                ys.append(y.to(torch.float32) / float(g.n_edges))
         g.close()
     return torch.cat(xs), torch.cat(ys)
 
@@ -150,8 +169,9 @@ def train(X, Y, epochs=20, batch=8192, lr=1e-3, seed=3, log=None, label="final")
     dev = X.device
     N = X.shape[0]
     mean = torch.zeros(16, dtype=torch.float32, device=dev)
-    std = torch.zeros(16, dtype=torch.float32, device=dev)
-    feature_stats(X, mean, std)
+    std = torch.ones(16, dtype=torch.float32, device=dev)
+    if label != "relative":  # relative rows are standardised within their population already
+        feature_stats(X, mean, std)
     params = torch.zeros(5313, dtype=torch.float32, device=dev)
     mlp_init(seed, params)
     m = torch.zeros_like(params)

@@ -137,6 +137,19 @@ def test_feature_stats_match_numpy(ising):
     assert np.allclose(std.cpu().numpy(), ref_std, rtol=1e-5, atol=1e-6)
 
 
+@pytest.mark.parametrize("G,R,C", [(3, 1000, 16), (1, 8192, 16), (2, 37, 1), (4, 1, 3)])
+def test_standardize_groups_matches_oracle(ising, G, R, C):
+    rng = np.random.default_rng(G * 1000 + R + C)
+    x = (rng.standard_normal((G * R, C)) * rng.uniform(0.1, 50, C) + rng.uniform(-1e4, 1e4, C)).astype(np.float32)
+    x[: R, C - 1] = 0.25  # a column the first group shares
+    t = dev_tensor(x)
+    ising.standardize_groups(t, G, R, C)
+    ref = olearn.standardize_groups(x, G, R, C)
+    got = t.cpu().numpy()
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-5)
+    assert (got[:R, C - 1] == 0).all()
+
+
 def test_features_match_oracle_over_two_checkpoints(ising):
     import torch
 

@@ -11,7 +11,8 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-def test_learned_culling_reaches_target_faster_than_plain():
+@pytest.mark.parametrize("label", ["final", "relative"])
+def test_learned_culling_reaches_target_faster_than_plain(label):
     import torch
 
     assert torch.cuda.is_available()
@@ -19,7 +20,7 @@ def test_learned_culling_reaches_target_faster_than_plain():
 
     s = experiments.ttt_experiment(dims=(50, 100), weight_seed=3001, R=1024, S=4000, window=400,
                                    run_seeds=(201, 202, 203), train_seeds=(1001, 1002, 1003, 1004), n_traj=4096,
-                                   epochs=20, batch=8192, long_sweeps=4000, log=print)
+                                   epochs=20, batch=8192, long_sweeps=4000, label=label, log=print)
     blk = s["targets"]["compared_runs"]
     ttt = {m: blk["methods"][m]["median_TTT_s"] for m in blk["methods"]}
     print("target", blk["target"], "median TTT (s)", ttt)

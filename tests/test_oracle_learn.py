@@ -122,3 +122,30 @@ def test_cull_order_and_clone():
     # worst three (2, 4, 5) take the best three (6, 1, 3); the middle (0) stays
     assert spins[:, 0].tolist() == [0, 1, 6, 3, 1, 3, 6]
     assert tr["h_min"].tolist() == [0, 10, 60, 30, 10, 30, 60]
+
+
+def test_standardize_groups_closed_form_and_invariants():
+    """Within each group every column ends with mean 0 and population std 1;
+    [1, 2, 3] maps to -sqrt(3/2), 0, sqrt(3/2); a column the whole group shares
+    maps to 0; groups do not see each other."""
+    x = np.array([[1.0], [2.0], [3.0]], np.float32)
+    y = learn.standardize_groups(x, 1, 3, 1)
+    assert np.allclose(y[:, 0], [-math.sqrt(1.5), 0.0, math.sqrt(1.5)], atol=1e-7)
+    rng = np.random.default_rng(2)
+    G, R, C = 3, 50, 4
+    a = (rng.standard_normal((G, R, C)) * 7 + 100).astype(np.float32)
+    a[1, :, 2] = 5.0
+    z = learn.standardize_groups(a.reshape(G * R, C), G, R, C).reshape(G, R, C).astype(np.float64)
+    for g in range(G):
+        for c in range(C):
+            if (g, c) == (1, 2):
+                assert (z[g, :, c] == 0).all()
+            else:
+                assert abs(z[g, :, c].mean()) < 1e-6 and abs(z[g, :, c].std() - 1) < 1e-6
+    # shifting and scaling one group leaves every group's result unchanged
+    b = a.copy()
+    b[0] = b[0] * 3 + 11
+    z2 = learn.standardize_groups(b.reshape(G * R, C), G, R, C).reshape(G, R, C)
+    assert np.allclose(z2, z, atol=1e-5)
+    # a ranking by the standardised column is the ranking by the raw column
+    assert (np.argsort(z[0, :, 1], kind="stable") == np.argsort(a[0, :, 1], kind="stable")).all()
