@@ -51,7 +51,7 @@ def first_hit_seconds(window_best, target, S, seconds):
 
 def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000, run_seeds=(201, 202, 203, 204, 205),
                    train_seeds=tuple(range(1001, 1014)), n_traj=100000, epochs=20, batch=8192, long_sweeps=200000,
-                   label="final", train_dims=None, train_replicas=None, log=print):
+                   label="relative", train_dims=None, train_replicas=None, log=print):
     import torch
 
     t_start = time.time()
@@ -137,7 +137,7 @@ def main(argv=None):
     ap.add_argument("--seeds", type=int, default=5)
     ap.add_argument("--long-sweeps", type=int, default=200000)
     ap.add_argument("--out", default=None)
-    ap.add_argument("--label", choices=learn.LABELS, default="final")
+    ap.add_argument("--label", choices=learn.LABELS, default="relative")
     ap.add_argument("--dims", default="100x200")
     ap.add_argument("--weight-seed", type=int, default=81)
     ap.add_argument("--train-dims", default=None)
