@@ -5,7 +5,9 @@ S = 40,000 sweeps, geometric beta 0.05 -> 4.0, checkpoints every 2,000
 sweeps):
  1. training rows: plain runs on other instances (weight seeds 1001..1013),
     features at the 19 checkpoints of the first 100,000 trajectories,
-    labelled with their end-of-trial cut / |E|;
+    labelled (default "relative") with their end-of-trial cut's standing
+    among the run's replicas, the features standardised over the replicas
+    of their checkpoint;
  2. train the 16-64-64-1 network (Adam, lr 1e-3, batch 8,192, 20 epochs);
  3. for run seeds 201..205: plain, learned-cull and energy-cull runs;
  4. best = largest cut of any run, including one longer plain run;
