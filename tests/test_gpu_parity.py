@@ -123,6 +123,20 @@ def test_c2_first_200_sweeps_sampled_replicas(dev, layout):
         assert_same(gpu, orc, rows=slice(start, start + 4))
 
 
+def test_c2_full_schedule_in_bench_launch_sampled(dev):
+    """The timed configuration itself: all 1,024 replicas through the whole
+    10,000-sweep schedule in one launch of the automatically chosen packing;
+    the oracle recomputes the first and the last replica quad end to end."""
+    c = inputs.C2
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, c["S"], c["schedule"], c["beta0"],
+                  c["beta1"], layout="auto")
+    for start in (0, c["R"] - 4):
+        print("oracle quad", start, flush=True)
+        orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, c["S"], c["schedule"], c["beta0"],
+                         c["beta1"], replica_begin=start)
+        assert_same(gpu, orc, rows=slice(start, start + 4))
+
+
 def test_c2_layouts_agree_on_every_replica(dev):
     """i8, bp32 and bs4 packings give identical spins, cuts, energies and
     flip counts on all 1,024 replicas of sweeps [0, 200)."""

@@ -99,6 +99,37 @@ def test_tempering_run_matches_oracle(ising, dims):
     g.close()
 
 
+def test_tempering_full_shape_matches_oracle(ising):
+    """The shape the tempering experiment runs: 100x200 torus, 32 ladders of
+    32 temperatures (1,024 replicas, 256 quads), three rounds of 10 sweeps;
+    every spin, energy, label and accepted count against the oracle."""
+    import torch
+
+    dims = [100, 200]
+    n = oracle.n_sites(dims)
+    betas = list(np.geomspace(0.5, 3.0, 32))
+    L, Q, E, seed = 32, 3, 10, 401
+    w = oracle.random_weights(81, 2 * n)
+    g = ising.create_graph(dims, 81)
+    p = ising.PT(g, betas, L, seed)
+    spins = torch.zeros((L * 32, n), dtype=torch.int8, device="cuda")
+    en = torch.zeros(L * 32, dtype=torch.int64, device="cuda")
+    p.run(spins, Q, E, init_spins=True, energy=en)
+    labels = p.labels().cpu().numpy()
+    acc = p.accepted()
+    rs, ren, rk, rpos, log = opt.run_pt(dims, w, seed, betas, L, Q, E)
+    torch.cuda.synchronize()
+    assert (spins.cpu().numpy() == rs).all()
+    assert (en.cpu().numpy() == ren).all() and (labels == rk).all()
+    counts = np.zeros(31, np.int64)
+    for a in log:
+        for _, k in a:
+            counts[k] += 1
+    assert (acc.astype(np.int64) == counts).all()
+    p.close()
+    g.close()
+
+
 def test_tempering_resumes_and_equal_temperatures_swap(ising):
     import torch
 
