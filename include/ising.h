@@ -69,7 +69,7 @@ enum {
   ISING_LAYOUT_STREAM = 3, /* 32 replicas per word, state in HBM, one launch per */
                            /* colour half-sweep (lattices too large for LDS)     */
   ISING_LAYOUT_BS4 = 4     /* 4 replicas x 4 sites per 16-bit word, bit-sliced;  */
-                           /* needs the second-fastest axis divisible by 4       */
+                           /* 3-D needs Ly divisible by 4; 2-D takes any rows    */
 };
 
 /* A cut or energy that could not be computed because the replica's spins

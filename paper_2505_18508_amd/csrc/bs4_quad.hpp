@@ -10,7 +10,10 @@
 // Word g = gl * hx + m of colour p holds the colour-p sites at column m
 // (x = 2m + o) of the lines 4 gl .. 4 gl + 3 (line = z Ly + y; the lines of
 // a word share z because Ly is a multiple of 4); bit 4 j + r is the spin
-// (1: +1) of replica 4q + r at line 4 gl + j.  LDS holds one record of
+// (1: +1) of replica 4q + r at line 4 gl + j.  A 2-D torus whose row count
+// is 2 mod 4 (variant PART) has a last word line of two rows: its nibbles
+// 2 and 3 are padding, held at 0 and never flipped, and the y neighbours
+// across the wrap are shifted in by one nibble instead of three.  LDS holds one record of
 // 32-bit entries per g: the colour-0 and colour-1 words, then per colour one
 // weight mask per direction slot (nibble j all ones iff that bond of site j
 // has weight +1); the record stride is odd, so a wave's records fall in
@@ -87,9 +90,10 @@ struct Bs4Walk {
 
 // Unsatisfied bonds of the 16 lanes of colour-P word at record `base`,
 // counted bit-sliced: u = u0 + 2 u1 + 4 u2.
-template <int NDIM, int P>
+template <int NDIM, int P, bool PART = false>
 __device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const Bs4Walk& wk, uint32_t Y, uint32_t z,
                                           uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+  static_assert(!PART || NDIM == 2, "two-row word lines are a 2-D variant");
   constexpr int DEG = 2 * NDIM;
   constexpr int O = 1 - P;
   const uint32_t* rec = (const uint32_t*)(lds + base);
@@ -106,8 +110,14 @@ __device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const 
   uint32_t nb[DEG];
   nb[0] = xs;
   nb[1] = (xu & sel) | (xd & ~sel);
-  nb[2] = (xs >> 4) | (yn << 12);
-  nb[3] = (xs << 4) | (yv >> 12);
+  if (PART) {
+    // row Ly - 1 is nibble 1 of the last word line, so the wrap shifts by one nibble
+    nb[2] = (xs >> 4) | (yn << (Y + 1u == wk.LY4 ? 4u : 12u));
+    nb[3] = (xs << 4) | (yv >> (Y == 0u ? 4u : 12u));
+  } else {
+    nb[2] = (xs >> 4) | (yn << 12);
+    nb[3] = (xs << 4) | (yv >> 12);
+  }
   if (NDIM == 3) {
     const uint32_t vol = wk.plane * wk.Lz;
     const uint32_t zp = (z + 1u == wk.Lz) ? base + wk.plane - vol : base + wk.plane;
@@ -162,7 +172,7 @@ __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t 
 }
 
 // One half-sweep of colour P over this thread's words.
-template <int NDIM, int P, bool FLIPS, bool STATS, bool PT>
+template <int NDIM, int P, bool FLIPS, bool STATS, bool PT, bool PART>
 __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4Args& a, int t, uint32_t quad,
                                          const QuadThr& th, uint32_t T1, uint32_t T2, uint32_t T3,
                                          uint32_t valid16, uint32_t* fl, uint32_t& n_blocks,
@@ -176,7 +186,8 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
       z = 0u;
     }
     uint32_t s, u0, u1, u2;
-    bs4_bonds<NDIM, P>(lds, base, wk, Y, z, s, u0, u1, u2);
+    bs4_bonds<NDIM, P, PART>(lds, base, wk, Y, z, s, u0, u1, u2);
+    const uint32_t rows = (PART && Y + 1u == wk.LY4) ? 0x00FFu : 0xFFFFu;  // lanes of real sites
     // dE = 2 deg - 4u: flip when u >= deg/2; else k = deg/2 - u
     uint32_t acc, k1, k2, k3 = 0u;
     if (NDIM == 2) {
@@ -203,12 +214,12 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
       else
         bs4_draws<3, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
       if (STATS) {  // schedule only: per-replica thresholds reject statistics
-        const uint32_t need = (k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & valid16;
+        const uint32_t need = (k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & valid16 & rows;
         n_blocks += 4u;
         n_draws += __popc(need);
       }
     }
-    const uint32_t F = (acc | (k1 & c1) | (k2 & c2) | (k3 & c3)) & 0xFFFFu;
+    const uint32_t F = (acc | (k1 & c1) | (k2 & c2) | (k3 & c3)) & rows;
     if (F) ((uint32_t*)(lds + base))[P] = s ^ F;
     if (FLIPS) {
 #pragma unroll
@@ -232,14 +243,16 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
 // bytes of records and extra kExtraWords words.
 // PT: the replicas run at their own fixed temperatures (a.rep_thr) instead
 // of the schedule's (a.thr).
-template <int NDIM, bool FLIPS, bool STATS, bool PT = false>
+// PART: a 2-D torus with rows = 2 mod 4 (last word line of two rows).
+template <int NDIM, bool FLIPS, bool STATS, bool PT = false, bool PART = false>
 __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_t* lds, uint32_t* extra) {
+  static_assert(!PART || NDIM == 2, "two-row word lines are a 2-D variant");
   constexpr int DEG = 2 * NDIM;
   constexpr uint32_t RS = (uint32_t)rec_words<NDIM>();
   const Lattice& L = a.lat;
   const uint32_t hx = (uint32_t)L.hx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz, Lx = (uint32_t)L.Lx;
-  const uint32_t LY4 = Ly / 4u;                // word lines per plane
-  const uint32_t GL = (uint32_t)L.lines / 4u;  // word lines
+  const uint32_t LY4 = (Ly + 3u) / 4u;        // word lines per plane
+  const uint32_t GL = LY4 * Lz;                // word lines
   const uint32_t G = GL * hx;                  // records
   const int tid = threadIdx.x;
   const int B = blockDim.x;
@@ -264,12 +277,13 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
     for (int d = 0; d < DEG; ++d) wm0[d] = wm1[d] = 0u;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const uint32_t line = 4u * gl + (uint32_t)j;
-      const uint32_t y = line - z * Ly;
+      const uint32_t y = 4u * (gl - z * LY4) + (uint32_t)j;
+      const bool real = !PART || y < Ly;  // else a padding row of a two-row word line
+      const uint32_t line = z * Ly + (real ? y : y - 2u);  // padding rows load row y - 2 and drop it
       const uint32_t o0 = (y + z) & 1u;  // colour 0 sits at x = 2m + o0, colour 1 at 2m + 1 - o0
       const uint32_t cb = line * Lx + 2u * m;
-      const uint32_t wb0 = a.wbits[line * hx + m];
-      const uint32_t wb1 = a.wbits[(uint32_t)L.half + line * hx + m];
+      const uint32_t wb0 = real ? a.wbits[line * hx + m] : 0xFFu;
+      const uint32_t wb1 = real ? a.wbits[(uint32_t)L.half + line * hx + m] : 0xFFu;
       // direction order -> slot order: x-same is +x at x offset 0, -x at offset 1
       const uint32_t ws0 = o0 ? ((wb0 & ~3u) | ((wb0 & 1u) << 1) | ((wb0 >> 1) & 1u)) : wb0;
       const uint32_t ws1 = o0 ? wb1 : ((wb1 & ~3u) | ((wb1 & 1u) << 1) | ((wb1 >> 1) & 1u));
@@ -283,14 +297,14 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         const u32x4 r1v = philox_lane_c0(a.seed, cb + 1u - o0, 0u, quad, kTagInit);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          w0 |= (r0v.v[b] >> 31) << (4 * j + b);
-          w1 |= (r1v.v[b] >> 31) << (4 * j + b);
+          w0 |= (real ? r0v.v[b] >> 31 : 0u) << (4 * j + b);
+          w1 |= (real ? r1v.v[b] >> 31 : 0u) << (4 * j + b);
         }
       } else {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int8_t ve = a.spins[row[b] + cb], vo = a.spins[row[b] + cb + 1u];  // x = 2m, 2m + 1
-          const uint32_t keep = b < nvalid ? 1u : 0u;
+          const uint32_t keep = (b < nvalid && real) ? 1u : 0u;
           const uint32_t ue = ve > 0 ? keep : 0u, uo = vo > 0 ? keep : 0u;
           w0 |= (o0 ? uo : ue) << (4 * j + b);
           w1 |= (o0 ? ue : uo) << (4 * j + b);
@@ -361,10 +375,10 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
       T3 = NDIM == 3 ? tr[2] : 0u;
     }
     if (active)
-      bs4_half<NDIM, 0, FLIPS, STATS, PT>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+      bs4_half<NDIM, 0, FLIPS, STATS, PT, PART>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
     __syncthreads();
     if (active)
-      bs4_half<NDIM, 1, FLIPS, STATS, PT>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+      bs4_half<NDIM, 1, FLIPS, STATS, PT, PART>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
     __syncthreads();
   }
 
@@ -379,10 +393,11 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         z = 0u;
       }
       uint32_t s, u0, u1, u2;
-      bs4_bonds<NDIM, 0>(lb, base, wk, Y, z, s, u0, u1, u2);
+      bs4_bonds<NDIM, 0, PART>(lb, base, wk, Y, z, s, u0, u1, u2);
+      const uint32_t rows = (PART && Y + 1u == LY4) ? 0x00FFu : 0xFFFFu;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const uint32_t mr = 0x1111u << b;
+        const uint32_t mr = (0x1111u << b) & rows;
         e[b] += __popc(u0 & mr) + 2u * __popc(u1 & mr) + 4u * __popc(u2 & mr);
       }
       base += wk.step;
@@ -415,13 +430,15 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
     const uint32_t w0 = lds[g * RS], w1 = lds[g * RS + 1u];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const uint32_t line = 4u * gl + (uint32_t)j;
-      const uint32_t o0 = (line - z * Ly + z) & 1u;
+      const uint32_t y = 4u * (gl - z * LY4) + (uint32_t)j;
+      const bool real = !PART || y < Ly;
+      const uint32_t line = z * Ly + y;
+      const uint32_t o0 = (y + z) & 1u;
       const uint32_t cb = line * Lx + 2u * m;
       const uint32_t we = o0 ? w1 : w0, wo = o0 ? w0 : w1;  // words holding x = 2m and 2m + 1
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        if (b < nvalid) {
+        if (b < nvalid && real) {
           const uint32_t sh = 4u * (uint32_t)j + (uint32_t)b;
           a.spins[row[b] + cb] = ((we >> sh) & 1u) ? (int8_t)1 : (int8_t)-1;
           a.spins[row[b] + cb + 1u] = ((wo >> sh) & 1u) ? (int8_t)1 : (int8_t)-1;

@@ -33,7 +33,8 @@ struct BatchItem {
 
 // One instance: its packing and the arguments of that packing's routine.
 struct BatchInst {
-  int32_t bs4;  // 1: bit-sliced 4 x 4, 0: byte per replica
+  int32_t bs4;   // 1: bit-sliced 4 x 4, 0: byte per replica
+  int32_t part;  // bs4 on a 2-D torus with rows = 2 mod 4 (two-row last word line)
   i8q::I8Args i8;
   bs4q::Bs4Args b4;
 };
@@ -53,12 +54,25 @@ __global__ void __launch_bounds__(kBatchBlock) k_sweep_batch(const BatchInst* in
     if (it >= n_items) break;
     const BatchItem bi = items[it];
     const BatchInst& I = inst[bi.inst];
-    if (I.bs4 && I.b4.rep_thr)
-      bs4q::bs4_quad<NDIM, true, false, true>(I.b4, bi.r0, lds, extra);
-    else if (I.bs4)
-      bs4q::bs4_quad<NDIM, true, false, false>(I.b4, bi.r0, lds, extra);
-    else
+    if (I.bs4) {
+      const bool pt = I.b4.rep_thr != nullptr;
+      if constexpr (NDIM == 2) {
+        if (I.part) {
+          if (pt)
+            bs4q::bs4_quad<2, true, false, true, true>(I.b4, bi.r0, lds, extra);
+          else
+            bs4q::bs4_quad<2, true, false, false, true>(I.b4, bi.r0, lds, extra);
+          __syncthreads();
+          continue;
+        }
+      }
+      if (pt)
+        bs4q::bs4_quad<NDIM, true, false, true>(I.b4, bi.r0, lds, extra);
+      else
+        bs4q::bs4_quad<NDIM, true, false, false>(I.b4, bi.r0, lds, extra);
+    } else {
       i8q::i8_quad<NDIM, false>(I.i8, bi.r0, lds, lut, extra);
+    }
     __syncthreads();
   }
 }
@@ -83,6 +97,7 @@ hipError_t build_batch(const ising_graph* const* graphs, const SweepLaunch* laun
     const Lattice& L = g->lat;
     BatchInst& I = inst[(size_t)k];
     I.bs4 = layouts[k] == ISING_LAYOUT_BS4 ? 1 : 0;
+    I.part = (I.bs4 && L.Ly % 4 != 0) ? 1 : 0;
     const int block = I.bs4 ? sweep_bs4_block(L, kBatchBlock) : sweep_i8_block(L, kBatchBlock);
     if (block <= 0) return hipErrorInvalidValue;
     auto fill = [&](auto& a) {

@@ -3,6 +3,8 @@
 // layout and the per-quad work are described in bs4_quad.hpp.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bs4_quad.hpp"
 #include "internal.hpp"
 
@@ -11,27 +13,34 @@ namespace {
 
 using namespace bs4q;
 
-template <int NDIM, bool FLIPS, bool STATS, bool PT>
+template <int NDIM, bool FLIPS, bool STATS, bool PT, bool PART>
 __global__ void __launch_bounds__(kMaxBlock) k_sweep_bs4(Bs4Args a) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t extra[kExtraWords];
-  bs4_quad<NDIM, FLIPS, STATS, PT>(a, blockIdx.x * 4, lds, extra);
+  bs4_quad<NDIM, FLIPS, STATS, PT, PART>(a, blockIdx.x * 4, lds, extra);
 }
+
+// word lines per plane: rows / 4, or (rows + 2) / 4 with a last two-row line
+int word_lines(const Lattice& L) { return (L.Ly + 3) / 4 * L.Lz; }
 
 }  // namespace
 
-bool sweep_bs4_supported(const Lattice& L) { return L.Ly % 4 == 0 && L.hx >= 1; }
+// 3-D tori need Ly divisible by 4; 2-D tori any even row count (rows = 2 mod
+// 4 take the variant with a two-row last word line)
+bool sweep_bs4_supported(const Lattice& L) {
+  return L.hx >= 1 && (L.Ly % 4 == 0 || (L.ndim == 2 && L.Ly % 4 == 2));
+}
 
 size_t sweep_bs4_dyn_lds(const Lattice& L) {
   const size_t rs = L.ndim == 2 ? (size_t)rec_words<2>() : (size_t)rec_words<3>();
-  return (size_t)L.n / 8u * rs * 4u;
+  return (size_t)word_lines(L) * (size_t)L.hx * rs * 4u;
 }
 
 size_t sweep_bs4_lds_bytes(const Lattice& L) { return sweep_bs4_dyn_lds(L) + kExtraWords * 4u; }
 
 int sweep_bs4_block(const Lattice& L, int requested) {
   if (!sweep_bs4_supported(L) || L.hx > kMaxBlock) return 0;
-  const int GL = L.lines / 4;
+  const int GL = word_lines(L);
   int max_lp = kMaxBlock / L.hx;
   if (max_lp > GL) max_lp = GL;
   int lp = max_lp;
@@ -75,15 +84,21 @@ hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStrea
   };
   const bool fl = s.flips != nullptr, st = s.stats != nullptr;
   hipError_t e;
-  if (s.rep_thr) {  // replica exchange: no RNG statistics variant
-    if (g->ndim == 2) e = fl ? go(k_sweep_bs4<2, true, false, true>) : go(k_sweep_bs4<2, false, false, true>);
-    else e = fl ? go(k_sweep_bs4<3, true, false, true>) : go(k_sweep_bs4<3, false, false, true>);
-  } else if (g->ndim == 2) {
-    if (st) e = fl ? go(k_sweep_bs4<2, true, true, false>) : go(k_sweep_bs4<2, false, true, false>);
-    else e = fl ? go(k_sweep_bs4<2, true, false, false>) : go(k_sweep_bs4<2, false, false, false>);
+  // 2-D: PART selects the two-row last word line (rows = 2 mod 4)
+  auto go2 = [&](auto part) -> hipError_t {
+    constexpr bool P = decltype(part)::value;
+    if (s.rep_thr)  // replica exchange: no RNG statistics variant
+      return fl ? go(k_sweep_bs4<2, true, false, true, P>) : go(k_sweep_bs4<2, false, false, true, P>);
+    if (st) return fl ? go(k_sweep_bs4<2, true, true, false, P>) : go(k_sweep_bs4<2, false, true, false, P>);
+    return fl ? go(k_sweep_bs4<2, true, false, false, P>) : go(k_sweep_bs4<2, false, false, false, P>);
+  };
+  if (g->ndim == 2) {
+    e = L.Ly % 4 == 0 ? go2(std::false_type()) : go2(std::true_type());
+  } else if (s.rep_thr) {
+    e = fl ? go(k_sweep_bs4<3, true, false, true, false>) : go(k_sweep_bs4<3, false, false, true, false>);
   } else {
-    if (st) e = fl ? go(k_sweep_bs4<3, true, true, false>) : go(k_sweep_bs4<3, false, true, false>);
-    else e = fl ? go(k_sweep_bs4<3, true, false, false>) : go(k_sweep_bs4<3, false, false, false>);
+    if (st) e = fl ? go(k_sweep_bs4<3, true, true, false, false>) : go(k_sweep_bs4<3, false, true, false, false>);
+    else e = fl ? go(k_sweep_bs4<3, true, false, false, false>) : go(k_sweep_bs4<3, false, false, false, false>);
   }
   if (e != hipSuccess) return e;
   return hipGetLastError();

@@ -1,8 +1,8 @@
 """Persistent batches of uneven instances: every replica bit-identical to a
 single-instance run (itself pinned to the oracle), at small and full size,
-eagerly and replayed from a captured HIP graph.  Instances whose rows are a
-multiple of 4 take the bit-sliced 4 x 4 routine, the others the byte-per-
-replica one, in the same launch."""
+eagerly and replayed from a captured HIP graph.  2-D instances take the
+bit-sliced 4 x 4 routine (with a two-row last word line where the rows are
+2 mod 4), forced ones the byte-per-replica routine, in the same launch."""
 import numpy as np
 import pytest
 
@@ -150,11 +150,12 @@ def test_batch_argument_errors(ising):
 
 
 def test_mixed_and_forced_layouts_in_one_batch(ising):
-    """Forced i8 and bs4 instances next to AUTO ones (which take bs4 where the
-    rows allow it): every replica equals its single-instance run."""
+    """Forced i8 and bs4 instances next to AUTO ones (bs4, two-row last word
+    lines at 6 and 10 rows): every replica equals its single-instance run."""
     graphs, runs = make_runs(ising, [([8, 6], 6, 21, 9, 300, 0, 300, "geometric", 0.05, 4.0),
                                      ([8, 6], 6, 21, 9, 300, 0, 300, "geometric", 0.05, 4.0),
-                                     ([6, 8], 7, 22, 6, 250, 0, 250, "linear", 0.1, 3.0)])
+                                     ([6, 8], 7, 22, 6, 250, 0, 250, "linear", 0.1, 3.0),
+                                     ([10, 12], 8, 23, 7, 200, 0, 200, "geometric", 0.05, 4.0)])
     runs[0]["layout"] = "i8"
     runs[1]["layout"] = "bs4"
     b = ising.Batch(graphs, runs)
@@ -165,7 +166,7 @@ def test_mixed_and_forced_layouts_in_one_batch(ising):
     for g, run in zip(graphs, runs):
         assert_run_equal(run, single(ising, g, run))
     b.close()
-    g = ising.create_graph([6, 8], 1)
+    g = ising.create_graph([4, 6, 8], 1)  # 3-D with Ly = 6: no bit-sliced words
     s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
     with pytest.raises(ising.IsingError) as e:
         ising.Batch([g], [dict(seed=1, n_sweeps=10, spins=s, layout="bs4")])

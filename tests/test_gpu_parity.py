@@ -11,13 +11,12 @@ pytestmark = pytest.mark.gpu
 
 SCHED = {"linear": oracle.SCHED_LINEAR, "geometric": oracle.SCHED_GEOMETRIC, "table": oracle.SCHED_TABLE}
 LAYOUTS = ["i8", "bp32", "stream", "bs4"]
-# a torus the 4 x 4 bit-sliced layout takes in place of C1 (its rows are not a multiple of 4)
-BS4_C1_DIMS = [48, 100]
 
 
 def bs4_ok(dims):
-    """The 4 x 4 bit-sliced layout needs the second-fastest axis (rows in 2-D) divisible by 4."""
-    return (dims[0] if len(dims) == 2 else dims[1]) % 4 == 0
+    """The 4 x 4 bit-sliced layout takes any 2-D torus (rows = 2 mod 4: a last
+    word line of two rows) and 3-D tori with Ly divisible by 4."""
+    return len(dims) == 2 or dims[1] % 4 == 0
 
 
 @pytest.fixture(scope="module")
@@ -102,7 +101,7 @@ def test_philox_stream_matches_oracle(dev):
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_c1_full_run_bit_exact(dev, layout):
     c = inputs.C1
-    dims = BS4_C1_DIMS if layout == "bs4" else c["dims"]
+    dims = c["dims"]  # 50 rows: the bit-sliced layout's last word line holds two
     gpu = run_gpu(dims, c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
                   beta0=c["beta0"], beta1=c["beta1"], layout=layout)
     orc = run_oracle(dims, c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
@@ -219,7 +218,7 @@ def test_replica_offset_selects_streams(dev, layout):
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_block_size_does_not_change_results(dev, bt, layout):
     c = inputs.C1
-    dims = BS4_C1_DIMS if layout == "bs4" else c["dims"]
+    dims = c["dims"]
     ref = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", layout="i8")
     got = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", block_threads=bt, layout=layout)
     for x, y in zip(ref, got):
@@ -253,8 +252,9 @@ def test_too_large_torus_is_rejected(dev):
         assert e.value.code == ising.E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("dims", [[50, 100], [6, 8], [4, 6, 8]])
-def test_bs4_rejects_rows_not_divisible_by_4(dev, dims):
+@pytest.mark.parametrize("dims", [[4, 6, 8], [2, 2, 4], [6, 10, 6]])
+def test_bs4_rejects_3d_rows_not_divisible_by_4(dev, dims):
+    """3-D bit-sliced words need Ly divisible by 4 (2-D tori take two-row last word lines)."""
     import torch
 
     ising = _ising()
@@ -381,9 +381,10 @@ def test_streamed_matches_on_chip_layouts(dev):
         assert (x == y).all() and (x == z).all()
 
 
-@pytest.mark.parametrize("dims,R,want", [([100, 100], 1024, "bs4"), ([100, 200], 8192, "bp32"), ([50, 100], 16, "i8"),
+@pytest.mark.parametrize("dims,R,want", [([100, 100], 1024, "bs4"), ([100, 200], 8192, "bp32"), ([50, 100], 16, "bs4"),
                                          ([1000, 1000], 256, "stream"), ([200, 202], 4, "i8"),
-                                         ([64, 64, 64], 256, "stream"), ([16, 16, 16], 40, "bs4")])
+                                         ([64, 64, 64], 256, "stream"), ([16, 16, 16], 40, "bs4"),
+                                         ([8, 6, 8], 8, "i8")])
 def test_select_layout_reports_the_auto_choice(dev, dims, R, want):
     ising = _ising()
     g = ising.create_graph(dims, 1)

@@ -14,9 +14,14 @@ def test_candidates_cover_packings_and_tiles():
     assert all(bt % 50 == 0 and 0 < bt <= 1024 for _, bt in c)  # multiples of Lx/2 = 50
     # bs4 word lines hold 4 rows: at most 100 / 4 = 25 of them per pass
     assert all(bt <= 25 * 50 for l, bt in c if l == "bs4")
-    # too few 32-replica groups: the bit-packed layout is not a candidate; 50 rows: no bs4
-    assert {l for l, _ in tune.candidates([50, 100], 16)} == {"i8"}
+    # too few 32-replica groups: the bit-packed layout is not a candidate; 50 rows: 13 word
+    # lines, the last of two rows
+    c50 = tune.candidates([50, 100], 16)
+    assert {l for l, _ in c50} == {"i8", "bs4"}
+    assert all(bt <= 13 * 50 for l, bt in c50 if l == "bs4")
     assert {l for l, _ in tune.candidates([48, 100], 16)} == {"i8", "bs4"}
+    # 3-D: the bit-sliced words need Ly divisible by 4
+    assert {l for l, _ in tune.candidates([4, 6, 8], 16)} == {"i8"}
     assert tune.candidates([2, 4096], 64) == []  # a line wider than a block
 
 
