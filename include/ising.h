@@ -69,7 +69,7 @@ enum {
   ISING_LAYOUT_STREAM = 3, /* 32 replicas per word, state in HBM, one launch per */
                            /* colour half-sweep (lattices too large for LDS)     */
   ISING_LAYOUT_BS4 = 4     /* 4 replicas x 4 sites per 16-bit word, bit-sliced;  */
-                           /* 3-D needs Ly divisible by 4; 2-D takes any rows    */
+                           /* any even torus that fits a block's LDS             */
 };
 
 /* A cut or energy that could not be computed because the replica's spins

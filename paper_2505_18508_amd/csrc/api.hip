@@ -428,7 +428,7 @@ int check_run(const ising_graph* g, const ising_run_params* p, const int8_t* spi
   if (layout != ISING_LAYOUT_I8 && layout != ISING_LAYOUT_BP32 && layout != ISING_LAYOUT_BS4)
     return fail(ISING_E_ARG, "unknown layout %d", p->layout);
   if (layout == ISING_LAYOUT_BS4 && !ising::sweep_bs4_supported(g->lat))
-    return fail(ISING_E_UNSUPPORTED, "layout %d on a 3-D torus needs Ly divisible by 4", layout);
+    return fail(ISING_E_UNSUPPORTED, "torus too small for layout %d", layout);
   if ((layout == ISING_LAYOUT_I8 && !i8_fits) || (layout == ISING_LAYOUT_BP32 && !bp_fits) ||
       (layout == ISING_LAYOUT_BS4 && !bs4_fits))
     return fail(ISING_E_UNSUPPORTED, "torus of %lld sites does not fit the on-chip sweep kernel of layout %d",

@@ -31,24 +31,13 @@ __device__ __forceinline__ void bond_count3(const uint32_t* x, uint32_t& u0, uin
   }
 }
 
-// c = 2 c + (x < T): the borrow of x - T is shifted into c by one add with
-// carry, two VALU instructions per compare (T uniform).
-__device__ __forceinline__ uint32_t lt_shift_in(uint32_t c, uint32_t x, uint32_t T) {
-  uint32_t diff;
-  asm("v_subrev_co_u32_e32 %0, vcc, %2, %3\n\t"
-      "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc"
-      : "=&v"(diff), "+v"(c)
-      : "s"(T), "v"(x)
-      : "vcc");
-  return c;
-}
-
 // The four words of one Philox block shifted into LEV compare chains at once
 // (word 3 first), word b against its own thresholds T_k[b] (the four
 // replicas of a quad may run at different temperatures; all are uniform
 // over the block): c_k = 16 c_k + bits (u_3 < T_k[3], ..., u_0 < T_k[0]).
-// One asm block per Philox block keeps the carry sequence free of inserted
-// waits.
+// Each compare is two VALU instructions: the borrow of u - T, then an add
+// with carry that doubles c_k and shifts the borrow in.  One asm block per
+// Philox block keeps the carry sequence free of inserted waits.
 template <int LEV>
 __device__ __forceinline__ void lt_shift_in4(uint32_t& c1, uint32_t& c2, uint32_t& c3, const uint32_t* u,
                                              const uint32_t* T1, const uint32_t* T2, const uint32_t* T3) {
@@ -87,12 +76,34 @@ __device__ __forceinline__ void lt_shift_in4(uint32_t& c1, uint32_t& c2, uint32_
           "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
         : "vcc");
   } else {
-#pragma unroll
-    for (int b = 3; b >= 0; --b) {
-      c1 = lt_shift_in(c1, u[b], T1[b]);
-      c2 = lt_shift_in(c2, u[b], T2[b]);
-      c3 = lt_shift_in(c3, u[b], T3[b]);
-    }
+    asm("v_subrev_co_u32_e32 %0, vcc, %4, %16\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %8, %16\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %12, %16\n\t"
+        "v_addc_co_u32_e32 %3, vcc, %3, %3, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %5, %17\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %9, %17\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %13, %17\n\t"
+        "v_addc_co_u32_e32 %3, vcc, %3, %3, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %6, %18\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %10, %18\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %14, %18\n\t"
+        "v_addc_co_u32_e32 %3, vcc, %3, %3, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %7, %19\n\t"
+        "v_addc_co_u32_e32 %1, vcc, %1, %1, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %11, %19\n\t"
+        "v_addc_co_u32_e32 %2, vcc, %2, %2, vcc\n\t"
+        "v_subrev_co_u32_e32 %0, vcc, %15, %19\n\t"
+        "v_addc_co_u32_e32 %3, vcc, %3, %3, vcc"
+        : "=&v"(d), "+v"(c1), "+v"(c2), "+v"(c3)
+        : "s"(T1[3]), "s"(T1[2]), "s"(T1[1]), "s"(T1[0]), "s"(T2[3]), "s"(T2[2]), "s"(T2[1]), "s"(T2[0]),
+          "s"(T3[3]), "s"(T3[2]), "s"(T3[1]), "s"(T3[0]), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+        : "vcc");
   }
 }
 

@@ -7,13 +7,13 @@
 // with each replica quad into one 16-bit word, so that the bond logic of a
 // visit serves 16 (site, replica) attempts at once.
 //
-// Word g = gl * hx + m of colour p holds the colour-p sites at column m
-// (x = 2m + o) of the lines 4 gl .. 4 gl + 3 (line = z Ly + y; the lines of
-// a word share z because Ly is a multiple of 4); bit 4 j + r is the spin
-// (1: +1) of replica 4q + r at line 4 gl + j.  A 2-D torus whose row count
-// is 2 mod 4 (variant PART) has a last word line of two rows: its nibbles
-// 2 and 3 are padding, held at 0 and never flipped, and the y neighbours
-// across the wrap are shifted in by one nibble instead of three.  LDS holds one record of
+// Word g = gl * hx + m of colour p, gl = z LY4 + Y (LY4 = ceil(Ly / 4) word
+// lines per plane), holds the colour-p sites at column m (x = 2m + o) of
+// rows y = 4Y .. 4Y + 3 of plane z; bit 4 j + r is the spin (1: +1) of
+// replica 4q + r at row 4Y + j.  When Ly = 2 mod 4 (variant PART) the last
+// word line of every plane holds two rows: its nibbles 2 and 3 are padding,
+// held at 0 and never flipped, and the y neighbours across the wrap are
+// shifted in by one nibble instead of three.  LDS holds one record of
 // 32-bit entries per g: the colour-0 and colour-1 words, then per colour one
 // weight mask per direction slot (nibble j all ones iff that bond of site j
 // has weight +1); the record stride is odd, so a wave's records fall in
@@ -84,7 +84,8 @@ struct Bs4Walk {
   uint32_t step;           // records of lp word lines
   uint32_t row, plane;     // records of one word line / one plane
   uint32_t Y0, z0, lp_y, lp_z, LY4, Lz;
-  uint32_t ci0, ci_step;   // canonical index of (line 4 gl0, x = 2m), per pass
+  uint32_t ci0, ci_step;   // canonical index of (first line of word line gl0, x = 2m), per pass
+  uint32_t ci_m;           // 2m
   uint32_t GL, gl0, lp;
 };
 
@@ -93,7 +94,6 @@ struct Bs4Walk {
 template <int NDIM, int P, bool PART = false>
 __device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const Bs4Walk& wk, uint32_t Y, uint32_t z,
                                           uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
-  static_assert(!PART || NDIM == 2, "two-row word lines are a 2-D variant");
   constexpr int DEG = 2 * NDIM;
   constexpr int O = 1 - P;
   const uint32_t* rec = (const uint32_t*)(lds + base);
@@ -226,7 +226,6 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
       for (int b = 0; b < 4; ++b) fl[b] += __popc(F & (0x1111u << b));
     }
     base += wk.step;
-    ci0 += wk.ci_step;
     if (NDIM == 3) {
       Y += wk.lp_y;
       z += wk.lp_z;
@@ -235,6 +234,10 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
         z += 1u;
       }
     }
+    if (NDIM == 3 && PART)  // planes of Ly = 4 LY4 - 2 lines: the first line of word line (z, Y)
+      ci0 = (z * (uint32_t)a.lat.Ly + 4u * Y) * Lx + wk.ci_m;
+    else
+      ci0 += wk.ci_step;
   }
 }
 
@@ -243,10 +246,9 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
 // bytes of records and extra kExtraWords words.
 // PT: the replicas run at their own fixed temperatures (a.rep_thr) instead
 // of the schedule's (a.thr).
-// PART: a 2-D torus with rows = 2 mod 4 (last word line of two rows).
+// PART: Ly = 2 mod 4 (the last word line of every plane holds two rows).
 template <int NDIM, bool FLIPS, bool STATS, bool PT = false, bool PART = false>
 __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_t* lds, uint32_t* extra) {
-  static_assert(!PART || NDIM == 2, "two-row word lines are a 2-D variant");
   constexpr int DEG = 2 * NDIM;
   constexpr uint32_t RS = (uint32_t)rec_words<NDIM>();
   const Lattice& L = a.lat;
@@ -345,8 +347,9 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   wk.step = lp * hx * RS * 4u;
   wk.row = hx * RS * 4u;
   wk.plane = LY4 * wk.row;
-  wk.ci0 = 4u * gl0 * Lx + 2u * m;
+  wk.ci0 = (wk.z0 * Ly + 4u * wk.Y0) * Lx + 2u * m;  // = 4 gl0 Lx + 2m when Ly = 4 LY4
   wk.ci_step = 4u * lp * Lx;
+  wk.ci_m = 2u * m;
   wk.GL = GL;
   wk.gl0 = gl0;
   wk.lp = lp;

@@ -34,7 +34,7 @@ struct BatchItem {
 // One instance: its packing and the arguments of that packing's routine.
 struct BatchInst {
   int32_t bs4;   // 1: bit-sliced 4 x 4, 0: byte per replica
-  int32_t part;  // bs4 on a 2-D torus with rows = 2 mod 4 (two-row last word line)
+  int32_t part;  // bs4 with Ly = 2 mod 4 (two-row last word line of each plane)
   i8q::I8Args i8;
   bs4q::Bs4Args b4;
 };
@@ -56,20 +56,16 @@ __global__ void __launch_bounds__(kBatchBlock) k_sweep_batch(const BatchInst* in
     const BatchInst& I = inst[bi.inst];
     if (I.bs4) {
       const bool pt = I.b4.rep_thr != nullptr;
-      if constexpr (NDIM == 2) {
-        if (I.part) {
-          if (pt)
-            bs4q::bs4_quad<2, true, false, true, true>(I.b4, bi.r0, lds, extra);
-          else
-            bs4q::bs4_quad<2, true, false, false, true>(I.b4, bi.r0, lds, extra);
-          __syncthreads();
-          continue;
-        }
-      }
-      if (pt)
+      if (I.part) {
+        if (pt)
+          bs4q::bs4_quad<NDIM, true, false, true, true>(I.b4, bi.r0, lds, extra);
+        else
+          bs4q::bs4_quad<NDIM, true, false, false, true>(I.b4, bi.r0, lds, extra);
+      } else if (pt) {
         bs4q::bs4_quad<NDIM, true, false, true>(I.b4, bi.r0, lds, extra);
-      else
+      } else {
         bs4q::bs4_quad<NDIM, true, false, false>(I.b4, bi.r0, lds, extra);
+      }
     } else {
       i8q::i8_quad<NDIM, false>(I.i8, bi.r0, lds, lut, extra);
     }

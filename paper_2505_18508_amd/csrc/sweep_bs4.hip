@@ -25,11 +25,9 @@ int word_lines(const Lattice& L) { return (L.Ly + 3) / 4 * L.Lz; }
 
 }  // namespace
 
-// 3-D tori need Ly divisible by 4; 2-D tori any even row count (rows = 2 mod
-// 4 take the variant with a two-row last word line)
-bool sweep_bs4_supported(const Lattice& L) {
-  return L.hx >= 1 && (L.Ly % 4 == 0 || (L.ndim == 2 && L.Ly % 4 == 2));
-}
+// every even torus: Ly = 2 mod 4 takes the variant whose last word line of a
+// plane holds two rows
+bool sweep_bs4_supported(const Lattice& L) { return L.hx >= 1 && L.Ly % 2 == 0; }
 
 size_t sweep_bs4_dyn_lds(const Lattice& L) {
   const size_t rs = L.ndim == 2 ? (size_t)rec_words<2>() : (size_t)rec_words<3>();
@@ -84,22 +82,22 @@ hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStrea
   };
   const bool fl = s.flips != nullptr, st = s.stats != nullptr;
   hipError_t e;
-  // 2-D: PART selects the two-row last word line (rows = 2 mod 4)
-  auto go2 = [&](auto part) -> hipError_t {
+  // PART selects the two-row last word line (Ly = 2 mod 4)
+  auto pick = [&](auto ndim, auto part) -> hipError_t {
+    constexpr int D = decltype(ndim)::value;
     constexpr bool P = decltype(part)::value;
     if (s.rep_thr)  // replica exchange: no RNG statistics variant
-      return fl ? go(k_sweep_bs4<2, true, false, true, P>) : go(k_sweep_bs4<2, false, false, true, P>);
-    if (st) return fl ? go(k_sweep_bs4<2, true, true, false, P>) : go(k_sweep_bs4<2, false, true, false, P>);
-    return fl ? go(k_sweep_bs4<2, true, false, false, P>) : go(k_sweep_bs4<2, false, false, false, P>);
+      return fl ? go(k_sweep_bs4<D, true, false, true, P>) : go(k_sweep_bs4<D, false, false, true, P>);
+    if (st) return fl ? go(k_sweep_bs4<D, true, true, false, P>) : go(k_sweep_bs4<D, false, true, false, P>);
+    return fl ? go(k_sweep_bs4<D, true, false, false, P>) : go(k_sweep_bs4<D, false, false, false, P>);
   };
-  if (g->ndim == 2) {
-    e = L.Ly % 4 == 0 ? go2(std::false_type()) : go2(std::true_type());
-  } else if (s.rep_thr) {
-    e = fl ? go(k_sweep_bs4<3, true, false, true, false>) : go(k_sweep_bs4<3, false, false, true, false>);
-  } else {
-    if (st) e = fl ? go(k_sweep_bs4<3, true, true, false, false>) : go(k_sweep_bs4<3, false, true, false, false>);
-    else e = fl ? go(k_sweep_bs4<3, true, false, false, false>) : go(k_sweep_bs4<3, false, false, false, false>);
-  }
+  using two = std::integral_constant<int, 2>;
+  using three = std::integral_constant<int, 3>;
+  const bool part = L.Ly % 4 != 0;
+  if (g->ndim == 2)
+    e = part ? pick(two(), std::true_type()) : pick(two(), std::false_type());
+  else
+    e = part ? pick(three(), std::true_type()) : pick(three(), std::false_type());
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

@@ -38,9 +38,7 @@ def candidates(dims, n_replicas, cus=256):
     for layout in ("i8", "bp32", "bs4"):
         if layout == "bp32" and (n_replicas + 31) // 32 < cus // 8:
             continue  # fewer than one group per eight CUs: never competitive
-        if layout == "bs4" and L["Ly"] % 4 and len(dims) == 3:
-            continue  # four sites per word along y (2-D: a last word line of two rows)
-        word_lines = (L["Ly"] + 3) // 4 * L["Lz"]
+        word_lines = (L["Ly"] + 3) // 4 * L["Lz"]  # four rows per word line; Ly = 2 mod 4: a last one of two
         cand_lps = lps if layout != "bs4" else sorted({max(1, min(lp, word_lines)) for lp in lps})
         for lp in cand_lps:
             out.append((layout, lp * hx))

@@ -1,8 +1,8 @@
 """Persistent batches of uneven instances: every replica bit-identical to a
 single-instance run (itself pinned to the oracle), at small and full size,
-eagerly and replayed from a captured HIP graph.  2-D instances take the
-bit-sliced 4 x 4 routine (with a two-row last word line where the rows are
-2 mod 4), forced ones the byte-per-replica routine, in the same launch."""
+eagerly and replayed from a captured HIP graph.  Instances take the
+bit-sliced 4 x 4 routine (with a two-row last word line per plane where
+Ly = 2 mod 4), forced ones the byte-per-replica routine, in the same launch."""
 import numpy as np
 import pytest
 
@@ -166,7 +166,7 @@ def test_mixed_and_forced_layouts_in_one_batch(ising):
     for g, run in zip(graphs, runs):
         assert_run_equal(run, single(ising, g, run))
     b.close()
-    g = ising.create_graph([4, 6, 8], 1)  # 3-D with Ly = 6: no bit-sliced words
+    g = ising.create_graph([200, 204], 1)  # bit-sliced records beyond a block's LDS
     s = torch.zeros((4, g.n), dtype=torch.int8, device="cuda")
     with pytest.raises(ising.IsingError) as e:
         ising.Batch([g], [dict(seed=1, n_sweeps=10, spins=s, layout="bs4")])

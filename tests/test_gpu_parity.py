@@ -14,9 +14,9 @@ LAYOUTS = ["i8", "bp32", "stream", "bs4"]
 
 
 def bs4_ok(dims):
-    """The 4 x 4 bit-sliced layout takes any 2-D torus (rows = 2 mod 4: a last
-    word line of two rows) and 3-D tori with Ly divisible by 4."""
-    return len(dims) == 2 or dims[1] % 4 == 0
+    """The 4 x 4 bit-sliced layout takes every even torus (Ly = 2 mod 4: the
+    last word line of each plane holds two rows)."""
+    return True
 
 
 @pytest.fixture(scope="module")
@@ -252,9 +252,9 @@ def test_too_large_torus_is_rejected(dev):
         assert e.value.code == ising.E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("dims", [[4, 6, 8], [2, 2, 4], [6, 10, 6]])
-def test_bs4_rejects_3d_rows_not_divisible_by_4(dev, dims):
-    """3-D bit-sliced words need Ly divisible by 4 (2-D tori take two-row last word lines)."""
+@pytest.mark.parametrize("dims", [[200, 204], [40, 40, 40]])
+def test_bs4_rejects_lattices_too_large_for_lds(dev, dims):
+    """A forced bit-sliced packing of a lattice whose records exceed a block's LDS."""
     import torch
 
     ising = _ising()
@@ -384,7 +384,7 @@ def test_streamed_matches_on_chip_layouts(dev):
 @pytest.mark.parametrize("dims,R,want", [([100, 100], 1024, "bs4"), ([100, 200], 8192, "bp32"), ([50, 100], 16, "bs4"),
                                          ([1000, 1000], 256, "stream"), ([200, 202], 4, "i8"),
                                          ([64, 64, 64], 256, "stream"), ([16, 16, 16], 40, "bs4"),
-                                         ([8, 6, 8], 8, "i8")])
+                                         ([8, 6, 8], 8, "bs4")])
 def test_select_layout_reports_the_auto_choice(dev, dims, R, want):
     ising = _ising()
     g = ising.create_graph(dims, 1)

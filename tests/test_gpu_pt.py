@@ -23,7 +23,8 @@ def ising():
 
 
 @pytest.mark.parametrize("dims,layout", [([8, 12], "bs4"), ([8, 12], "i8"), ([6, 8], "i8"), ([6, 8], "bs4"),
-                                         ([2, 10], "bs4"), ([4, 4, 6], "bs4"), ([4, 6, 6], "i8")])
+                                         ([2, 10], "bs4"), ([4, 4, 6], "bs4"), ([4, 6, 6], "i8"),
+                                         ([4, 6, 6], "bs4")])
 def test_replica_thresholds_match_oracle(ising, dims, layout):
     import torch
 

@@ -20,8 +20,10 @@ def test_candidates_cover_packings_and_tiles():
     assert {l for l, _ in c50} == {"i8", "bs4"}
     assert all(bt <= 13 * 50 for l, bt in c50 if l == "bs4")
     assert {l for l, _ in tune.candidates([48, 100], 16)} == {"i8", "bs4"}
-    # 3-D: the bit-sliced words need Ly divisible by 4
-    assert {l for l, _ in tune.candidates([4, 6, 8], 16)} == {"i8"}
+    # 3-D with Ly = 6: two word lines per plane, the second of two rows
+    c3 = tune.candidates([4, 6, 8], 16)
+    assert {l for l, _ in c3} == {"i8", "bs4"}
+    assert all(bt <= 2 * 4 * 4 for l, bt in c3 if l == "bs4")
     assert tune.candidates([2, 4096], 64) == []  # a line wider than a block
 
 
