@@ -43,6 +43,7 @@
 #include "bitslice.hpp"
 #include "lattice.hpp"
 #include "philox.hpp"
+#include "reduce.hpp"
 
 namespace ising {
 namespace bs4q {
@@ -386,8 +387,8 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   }
 
   // ---- unsatisfied bonds of the colour-0 sites: energy -----------------------
+  uint32_t e[4] = {0u, 0u, 0u, 0u};
   if (active) {
-    uint32_t e[4] = {0u, 0u, 0u, 0u};
     uint32_t base = wk.base0;
     uint32_t Y = wk.Y0, z = wk.z0;
     for (uint32_t gl = gl0; gl < GL; gl += lp) {
@@ -413,15 +414,23 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         }
       }
     }
+  }
+  // wave totals first, then one atomic per wave and counter
+  const bool lane0 = (tid & 63) == 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      atomicAdd(&extra[8 + b], e[b]);
-      if (FLIPS) atomicAdd(&extra[b], fl[b]);
+  for (int b = 0; b < 4; ++b) {
+    const uint32_t es = wave_total(e[b]);
+    const uint32_t fs = FLIPS ? wave_total(fl[b]) : 0u;
+    if (lane0) {
+      atomicAdd(&extra[8 + b], es);
+      if (FLIPS) atomicAdd(&extra[b], fs);
     }
-    // per-thread totals go straight to the 64-bit outputs
-    if (STATS && (n_blocks | n_draws)) {
-      atomicAdd(&a.stats[0], (unsigned long long)n_blocks);
-      atomicAdd(&a.stats[1], (unsigned long long)n_draws);
+  }
+  if (STATS) {  // 64-bit: a block's totals can exceed 32 bits
+    const uint64_t nb = wave_total((uint64_t)n_blocks), nd = wave_total((uint64_t)n_draws);
+    if (lane0 && (nb | nd)) {
+      atomicAdd(&a.stats[0], (unsigned long long)nb);
+      atomicAdd(&a.stats[1], (unsigned long long)nd);
     }
   }
   __syncthreads();

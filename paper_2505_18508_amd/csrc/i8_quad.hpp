@@ -34,6 +34,7 @@
 
 #include "lattice.hpp"
 #include "philox.hpp"
+#include "reduce.hpp"
 
 namespace ising {
 namespace i8q {
@@ -429,19 +430,22 @@ __device__ __forceinline__ void i8_quad(const I8Args& a, const int r0, uint32_t*
         e3 += g >> 24;
       }
     }
-    atomicAdd(&extra[0], fl0);
-    atomicAdd(&extra[1], fl1);
-    atomicAdd(&extra[2], fl2);
-    atomicAdd(&extra[3], fl3);
-    atomicAdd(&extra[8], e0);
-    atomicAdd(&extra[9], e1);
-    atomicAdd(&extra[10], e2);
-    atomicAdd(&extra[11], e3);
-    // per-thread totals go straight to the 64-bit outputs (a block's total can
-    // exceed 32 bits)
-    if (STATS && (n_blocks | n_draws)) {
-      atomicAdd(&a.stats[0], (unsigned long long)n_blocks);
-      atomicAdd(&a.stats[1], (unsigned long long)n_draws);
+  }
+  // wave totals first, then one atomic per wave and counter
+  {
+    const uint32_t v[8] = {fl0, fl1, fl2, fl3, e0, e1, e2, e3};
+    const int slot[8] = {0, 1, 2, 3, 8, 9, 10, 11};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t s = wave_total(v[k]);
+      if ((tid & 63) == 0) atomicAdd(&extra[slot[k]], s);
+    }
+  }
+  if (STATS) {  // 64-bit: a block's totals can exceed 32 bits
+    const uint64_t nb = wave_total((uint64_t)n_blocks), nd = wave_total((uint64_t)n_draws);
+    if ((tid & 63) == 0 && (nb | nd)) {
+      atomicAdd(&a.stats[0], (unsigned long long)nb);
+      atomicAdd(&a.stats[1], (unsigned long long)nd);
     }
   }
   __syncthreads();

@@ -4,7 +4,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+extern "C" __device__ uint32_t __ockl_wfred_add_u32(uint32_t);
+extern "C" __device__ uint64_t __ockl_wfred_add_u64(uint64_t);
+
 namespace ising {
+
+// Sums over the active lanes of a wave (lanes a partial last wave does not
+// have count 0), returned to every active lane: the device library's
+// cross-lane reduction.  Used before one atomic per wave, since 64 lanes
+// adding to one LDS or global address are processed one lane at a time.
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) { return __ockl_wfred_add_u32(v); }
+__device__ __forceinline__ uint64_t wave_total(uint64_t v) { return __ockl_wfred_add_u64(v); }
 
 __device__ __forceinline__ int64_t wave_sum(int64_t v) {
 #pragma unroll

@@ -25,6 +25,7 @@
 #include "bitslice.hpp"
 #include "internal.hpp"
 #include "philox.hpp"
+#include "reduce.hpp"
 
 namespace ising {
 namespace {
@@ -74,18 +75,20 @@ __device__ __forceinline__ void bond_count(const uint32_t* x, uint32_t& u0, uint
 }
 
 // Per-lane value of a bit-sliced counter of NPLANES planes, added to LDS
-// counters dst[0..31] (lanes below nvalid only).
+// counters dst[0..31] (lanes below nvalid only): summed over the wave first,
+// then one atomic per wave and counter.  Every thread of the block calls it.
 template <int NPLANES>
 __device__ __forceinline__ void flush_planes(uint32_t* planes, uint32_t* dst, int nvalid) {
   uint32_t any = 0u;
 #pragma unroll
   for (int k = 0; k < NPLANES; ++k) any |= planes[k];
-  if (any == 0u) return;
+  if (__ballot(any != 0u) == 0ull) return;  // the whole wave has nothing to add
   for (int j = 0; j < nvalid; ++j) {
     uint32_t v = 0u;
 #pragma unroll
     for (int k = 0; k < NPLANES; ++k) v |= ((planes[k] >> j) & 1u) << k;
-    if (v) atomicAdd(&dst[j], v);
+    const uint32_t s = wave_total(v);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&dst[j], s);
   }
 #pragma unroll
   for (int k = 0; k < NPLANES; ++k) planes[k] = 0u;
@@ -299,11 +302,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
     }
     flush_planes<12>(eplanes, extra + 32, nvalid);
   }
-  // per-thread totals go straight to the 64-bit outputs (a block's total can
-  // exceed 32 bits)
-  if (STATS && (n_blocks | n_draws)) {
-    atomicAdd(&a.stats[0], (unsigned long long)n_blocks);
-    atomicAdd(&a.stats[1], (unsigned long long)n_draws);
+  // 64-bit totals (a block's can exceed 32 bits), one atomic per wave
+  if (STATS) {
+    const uint64_t nb = wave_total((uint64_t)n_blocks), nd = wave_total((uint64_t)n_draws);
+    if ((tid & 63) == 0 && (nb | nd)) {
+      atomicAdd(&a.stats[0], (unsigned long long)nb);
+      atomicAdd(&a.stats[1], (unsigned long long)nd);
+    }
   }
   __syncthreads();
 
