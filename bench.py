@@ -107,7 +107,7 @@ def cpu_baseline(budget_s):
     with concurrent.futures.ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
         futs = []
         r = 0
-        while r < cores:
+        while r < min(cores, WORKLOAD["R"]):
             futs.append(ex.submit(_oracle_one, r, w, WORKLOAD))
             r += 1
         while futs:

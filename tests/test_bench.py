@@ -1,0 +1,50 @@
+"""Host logic of bench.py (no GPU): the recorded HBM traffic is reported only
+while every source it was measured on is unchanged, more than one GPU is
+refused with a message, and the CPU-baseline leg times the oracle on a
+bounded sample."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    key = next(iter(rec))
+    kernel, workload = key.split("/")
+    for f in rec[key]["sources"]:
+        os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
+        shutil.copy(os.path.join(ROOT, f), tmp_path / f)
+    os.makedirs(tmp_path / "profiles")
+    shutil.copy(os.path.join(ROOT, "profiles", "traffic.json"), tmp_path / "profiles" / "traffic.json")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    want = rec[key]["fetch_bytes"] + rec[key]["write_bytes"]
+    assert bench.measured_traffic(kernel, workload) == pytest.approx(want)
+    assert bench.measured_traffic(kernel, "no-such-workload") is None
+    with open(tmp_path / rec[key]["sources"][-1], "a") as fh:
+        fh.write("\n// changed\n")
+    assert bench.measured_traffic(kernel, workload) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=300, cwd=ROOT)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr
+
+
+def test_cpu_baseline_times_the_oracle(monkeypatch):
+    wl = dict(bench.WORKLOAD, dims=[8, 8], R=3, S=40)
+    monkeypatch.setattr(bench, "WORKLOAD", wl)
+    res, done = bench.cpu_baseline(0.0)
+    assert res["kind"] == "oracle" and res["unit"] == "attempts/s" and res["value"] > 0
+    assert res["cores"] == min(os.cpu_count() or 1, 16)
+    assert sorted(r for r, _ in done) == list(range(min(3, res["cores"])))
+    assert all(s.shape == (64,) and set(s.tolist()) <= {-1, 1} for _, s in done)
