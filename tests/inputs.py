@@ -7,9 +7,9 @@ import numpy as np
 # Torus shapes of the workloads (2-D {rows, cols}, 3-D {Lz, Ly, Lx}): the
 # paper's toroidal grids of 5,000 / 10,000 / 14,000 / 20,000 spins
 # (Table I, Appendix A), and the 3-D degree-6 torus.
-C1 = dict(dims=[50, 100], weight_seed=1, seed=101, R=16, S=1000, schedule="linear", beta0=0.1, beta1=3.0)
-C2 = dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05, beta1=4.0)
-C4 = dict(dims=[100, 200], weight_seed=81, seed=201, R=8192, S=40000, schedule="geometric", beta0=0.05, beta1=4.0)
+TORUS_50x100_R16 = dict(dims=[50, 100], weight_seed=1, seed=101, R=16, S=1000, schedule="linear", beta0=0.1, beta1=3.0)
+TORUS_100x100_R1024 = dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05, beta1=4.0)
+TORUS_100x200_R8192 = dict(dims=[100, 200], weight_seed=81, seed=201, R=8192, S=40000, schedule="geometric", beta0=0.05, beta1=4.0)
 
 
 def random_spins(seed, n_replicas, n):

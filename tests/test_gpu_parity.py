@@ -99,8 +99,8 @@ def test_philox_stream_matches_oracle(dev):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_c1_full_run_bit_exact(dev, layout):
-    c = inputs.C1
+def test_torus50x100_full_run_bit_exact(dev, layout):
+    c = inputs.TORUS_50x100_R16
     dims = c["dims"]  # 50 rows: the bit-sliced layout's last word line holds two
     gpu = run_gpu(dims, c["weight_seed"], c["seed"], c["R"], c["S"], schedule=c["schedule"],
                   beta0=c["beta0"], beta1=c["beta1"], layout=layout)
@@ -110,10 +110,10 @@ def test_c1_full_run_bit_exact(dev, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_c2_first_200_sweeps_sampled_replicas(dev, layout):
+def test_torus100x100_first_200_sweeps_sampled_replicas(dev, layout):
     """All 1,024 replicas on the GPU for sweeps [0, 200) of the 10,000-sweep
     schedule; the oracle recomputes 24 of them (first, middle, last quads)."""
-    c = inputs.C2
+    c = inputs.TORUS_100x100_R1024
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
                   layout=layout)
     for start in (0, 4, 508, 512, 1016, 1020):
@@ -122,11 +122,11 @@ def test_c2_first_200_sweeps_sampled_replicas(dev, layout):
         assert_same(gpu, orc, rows=slice(start, start + 4))
 
 
-def test_c2_full_schedule_in_bench_launch_sampled(dev):
+def test_torus100x100_full_schedule_in_bench_launch_sampled(dev):
     """The timed configuration itself: all 1,024 replicas through the whole
     10,000-sweep schedule in one launch of the automatically chosen packing;
     the oracle recomputes the first and the last replica quad end to end."""
-    c = inputs.C2
+    c = inputs.TORUS_100x100_R1024
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, c["S"], c["schedule"], c["beta0"],
                   c["beta1"], layout="auto")
     for start in (0, c["R"] - 4):
@@ -136,10 +136,10 @@ def test_c2_full_schedule_in_bench_launch_sampled(dev):
         assert_same(gpu, orc, rows=slice(start, start + 4))
 
 
-def test_c2_layouts_agree_on_every_replica(dev):
+def test_torus100x100_layouts_agree_on_every_replica(dev):
     """i8, bp32 and bs4 packings give identical spins, cuts, energies and
     flip counts on all 1,024 replicas of sweeps [0, 200)."""
-    c = inputs.C2
+    c = inputs.TORUS_100x100_R1024
     a = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
                 layout="i8")
     for other in ("bp32", "bs4"):
@@ -150,9 +150,9 @@ def test_c2_layouts_agree_on_every_replica(dev):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_c4_shape_short_window_sampled(dev, layout):
+def test_torus100x200_short_window_sampled(dev, layout):
     """The 20,000-spin torus with 8,192 replicas (full launch shape), 30 sweeps."""
-    c = inputs.C4
+    c = inputs.TORUS_100x200_R8192
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 30, c["schedule"], c["beta0"], c["beta1"],
                   layout=layout)
     for start in (0, 4096, 8188):
@@ -217,7 +217,7 @@ def test_replica_offset_selects_streams(dev, layout):
 @pytest.mark.parametrize("bt", [1, 100, 300, 512, 1000])
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_block_size_does_not_change_results(dev, bt, layout):
-    c = inputs.C1
+    c = inputs.TORUS_50x100_R16
     dims = c["dims"]
     ref = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", layout="i8")
     got = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", block_threads=bt, layout=layout)
