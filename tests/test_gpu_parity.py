@@ -149,6 +149,21 @@ def test_torus100x100_layouts_agree_on_every_replica(dev):
             assert (x == y).all()
 
 
+def test_torus100x200_full_schedule_in_bench_launch_sampled(dev):
+    """The 20,000-spin workload as timed: all 8,192 replicas through the whole
+    40,000-sweep schedule in one launch of the automatically chosen packing
+    (32 replicas per word, flip counters flushed every few sweeps); the oracle
+    recomputes the last replica quad end to end."""
+    c = inputs.TORUS_100x200_R8192
+    gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, c["S"], c["schedule"], c["beta0"],
+                  c["beta1"], layout="auto")
+    start = c["R"] - 4
+    print("oracle quad", start, flush=True)
+    orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, c["S"], c["schedule"], c["beta0"],
+                     c["beta1"], replica_begin=start)
+    assert_same(gpu, orc, rows=slice(start, start + 4))
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_torus100x200_short_window_sampled(dev, layout):
     """The 20,000-spin torus with 8,192 replicas (full launch shape), 30 sweeps."""
