@@ -260,7 +260,8 @@ typedef struct ising_batch ising_batch;
  *   n_inst               >= 1 instances, all with the same ndim.
  *   graphs[k], params[k] instance k and its run (layout AUTO, I8 or BS4;
  *                        AUTO takes BS4 where the lattice allows it, else
- *                        I8; stats_out must be NULL).
+ *                        I8; stats_out must be NULL; replica_thresholds
+ *                        may be given, as for ising_run_trials).
  *   spins[k]             device int8 [R_k][n_k] (in/out, as ising_run_trials).
  *   cut_out, energy_out, flips_out  NULL, or arrays of n_inst device
  *                        pointers (entries may be NULL).

@@ -401,8 +401,9 @@ def energy_score(energy, score, stream=None):
 # ---------------------------------------------------------------------------
 class Batch:
     """A prepared persistent launch over several (graph, run) pairs.  Each run
-    is a dict of run_trials keyword arguments plus `spins` (device int8
-    [R][n]) and optional `cut`, `energy`, `flips` device tensors."""
+    is a dict of run_trials keyword arguments (replica_thresholds included)
+    plus `spins` (device int8 [R][n]) and optional `cut`, `energy`, `flips`
+    device tensors."""
 
     def __init__(self, graphs, runs):
         k = len(graphs)
@@ -416,10 +417,14 @@ class Batch:
             spins = run["spins"]
             if spins.dim() != 2 or spins.shape[1] != g.n:
                 raise ValueError("spins of instance %d must be [R][%d]" % (i, g.n))
+            rt = run.get("replica_thresholds")
+            if rt is not None and tuple(rt.shape) != (spins.shape[0], g.degree // 2):
+                raise ValueError("replica_thresholds of instance %d must be [R][%d]" % (i, g.degree // 2))
             p, keep = make_params(run["seed"], spins.shape[0], run["n_sweeps"], run.get("sweep_begin", 0),
                                   run.get("sweep_end"), run.get("schedule", "geometric"), run.get("beta0", 0.05),
                                   run.get("beta1", 4.0), run.get("beta_table"), run.get("init_spins", True),
-                                  run.get("layout", "auto"), 0, run.get("replica_offset", 0))
+                                  run.get("layout", "auto"), 0, run.get("replica_offset", 0),
+                                  replica_thresholds=rt)
             params[i] = p
             self._keep.append(keep)
             R = spins.shape[0]

@@ -557,9 +557,11 @@ int ising_batch_create(int32_t n_inst, const ising_graph* const* graphs, const i
     if (p->stats_out) return bail(fail(ISING_E_UNSUPPORTED, "batches do not collect RNG statistics"));
     uint32_t* d_thr = nullptr;
     bool owned = false;
-    rc = threshold_table(g, p, nullptr, &d_thr, &owned, true);
-    if (rc) return bail(rc);
-    if (owned) b->owned_tables.push_back(d_thr);  // kept for the plan's lifetime
+    if (!replica_thr(p)) {  // per-replica thresholds replace the schedule's table
+      rc = threshold_table(g, p, nullptr, &d_thr, &owned, true);
+      if (rc) return bail(rc);
+      if (owned) b->owned_tables.push_back(d_thr);  // kept for the plan's lifetime
+    }
     launches[(size_t)k] = make_launch(p, d_thr, spins[k], cut_out ? cut_out[k] : nullptr,
                                       energy_out ? energy_out[k] : nullptr, flips_out ? flips_out[k] : nullptr);
     b->attempts += (int64_t)p->n_replicas * g->n * (p->sweep_end - p->sweep_begin);

@@ -172,3 +172,49 @@ def test_mixed_and_forced_layouts_in_one_batch(ising):
         ising.Batch([g], [dict(seed=1, n_sweeps=10, spins=s, layout="bs4")])
     assert e.value.code == ising.E_UNSUPPORTED
 
+
+
+def test_batch_with_replica_thresholds_matches_single_runs(ising):
+    """Instances whose replicas run at their own fixed temperatures (the
+    replica-exchange sweeps) in one persistent launch: every replica equals
+    its single-instance run, and the first instance equals the oracle."""
+    import torch
+
+    from oracle import pt as opt
+
+    rng = np.random.default_rng(5)
+    specs = [([8, 12], 31, 7, 300), ([6, 10], 32, 6, 250), ([10, 12], 33, 9, 200), ([4, 4, 8], 34, 5, 150)]
+    graphs, runs, refs, rep0 = [], [], [], None
+    for dims, ws, R, S in specs:
+        g = ising.create_graph(dims, ws)
+        rep = opt.ladder_thresholds(rng.uniform(0.2, 2.0, R), len(dims))
+        if rep0 is None:
+            rep0 = rep
+        thr = torch.from_numpy(rep.astype(np.int32)).cuda()
+        run = dict(seed=40 + ws, n_sweeps=S, sweep_begin=0, sweep_end=S, schedule="linear", beta0=0.0, beta1=0.0,
+                   spins=torch.zeros((R, g.n), dtype=torch.int8, device="cuda"),
+                   cut=torch.zeros(R, dtype=torch.int64, device="cuda"),
+                   energy=torch.zeros(R, dtype=torch.int64, device="cuda"),
+                   flips=torch.zeros(R, dtype=torch.int32, device="cuda"), replica_thresholds=thr)
+        s2 = torch.zeros_like(run["spins"])
+        c2, e2 = torch.zeros_like(run["cut"]), torch.zeros_like(run["energy"])
+        f2 = torch.zeros_like(run["flips"])
+        ising.run_trials(g, s2, run["seed"], S, 0, S, "linear", 0.0, 0.0, None, True, "auto", c2, e2, f2,
+                         replica_thresholds=thr)
+        graphs.append(g)
+        runs.append(run)
+        refs.append((s2, c2, e2, f2))
+    b = ising.Batch(graphs[:3], runs[:3])  # one ndim per batch
+    b.run()
+    b3 = ising.Batch(graphs[3:], runs[3:])
+    b3.run()
+    torch.cuda.synchronize()
+    for run, ref in zip(runs, refs):
+        assert_run_equal(run, ref)
+    dims, ws, R, S = specs[0]
+    w = oracle.random_weights(ws, len(dims) * oracle.n_sites(dims))
+    ref, rfl = oracle.run_fixed(dims, w, runs[0]["seed"], rep0, 0, S)
+    assert (runs[0]["spins"].cpu().numpy() == ref).all()
+    assert (runs[0]["flips"].cpu().numpy().astype(np.uint32) == rfl).all()
+    for x in (b, b3):
+        x.close()
