@@ -57,15 +57,40 @@ def test_philox_matches_torch_engine(torch_philox):
         assert got == want, (key, ctr)
 
 
-def test_philox_words_uniform():
-    # top 4 bits of each output word, 16384 blocks: chi^2 against uniform
-    counts = np.zeros((4, 16), np.int64)
-    for c in range(16384):
-        out = oracle.philox(7, (c, 3, 5, 0))
-        for j in range(4):
-            counts[j, int(out[j]) >> 28] += 1
+@pytest.fixture(scope="module")
+def metropolis_words():
+    """2^20 Metropolis words: Philox blocks of (site, sweep, quad, tag 0) for
+    4,096 sites x 16 sweeps x 4 quads; column r = the word of replica 4q + r."""
+    out = np.zeros((4096 * 16 * 4, 4), np.uint32)
+    i = 0
+    for q in range(4):
+        for t in range(16):
+            for site in range(4096):
+                out[i] = oracle.philox(2024, (site, t, q, oracle.TAG_METROPOLIS))
+                i += 1
+    return out
+
+
+def test_philox_words_uniform(metropolis_words):
+    # 2^18 words per output position: chi^2 of the top and the bottom byte
+    # against uniform (256 bins, 1,024 expected per bin)
     for j in range(4):
-        assert stats.chisquare(counts[j]).pvalue > 1e-4
+        col = metropolis_words[:, j]
+        for byte in (col >> 24, col & 0xFF):
+            assert stats.chisquare(np.bincount(byte.astype(np.int64), minlength=256)).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("beta", [0.05, 0.2, 0.5])
+def test_metropolis_acceptance_frequency(metropolis_words, beta):
+    """The fraction of Metropolis words below T_k(beta) is exp(-4 k beta), the
+    Metropolis acceptance of dE = 4k (binomial z-test over 2^20 words)."""
+    u = metropolis_words.reshape(-1).astype(np.uint64)
+    N = u.size
+    for k in (1, 2, 3):
+        p = math.exp(-4 * k * beta)
+        hits = int(np.count_nonzero(u < oracle.threshold(beta, k)))
+        z = (hits - N * p) / math.sqrt(N * p * (1 - p))
+        assert abs(z) < 5, (beta, k, hits, N * p)
 
 
 # --------------------------------------------------------------------------
