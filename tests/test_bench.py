@@ -33,6 +33,29 @@ def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic(kernel, workload) is None
 
 
+def test_traffic_record_lists_every_included_source():
+    """The record's sources are the kernel file and the transitive closure of
+    its quoted includes, so no header the kernel is built from can change
+    unnoticed."""
+    import re
+
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    for key, r in rec.items():
+        todo, seen = [r["sources"][0]], set()
+        while todo:
+            f = todo.pop()
+            if f in seen:
+                continue
+            seen.add(f)
+            text = open(os.path.join(ROOT, f)).read()
+            for inc in re.findall(r'^#include "([^"]+)"', text, re.M):
+                path = os.path.normpath(os.path.join(os.path.dirname(f), inc))
+                if not os.path.exists(os.path.join(ROOT, path)):
+                    path = os.path.normpath(os.path.join("include", inc))
+                todo.append(path)
+        assert set(r["sources"]) == seen, key
+
+
 def test_more_than_one_gpu_is_refused():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                          text=True, timeout=300, cwd=ROOT)
