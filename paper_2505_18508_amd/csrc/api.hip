@@ -171,7 +171,9 @@ int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t
     std::lock_guard<std::mutex> lock(g->mu);
     for (const ThrCacheEntry& e : g->thr_cache)
       if (e.schedule == p->schedule && e.n_sweeps == p->n_sweeps && e.kmax == kmax && e.beta0 == b0 &&
-          e.beta1 == b1 && e.table_hash == th) {
+          e.beta1 == b1 && e.table_hash == th &&
+          (p->schedule != ISING_SCHED_TABLE ||
+           std::memcmp(e.table.data(), p->beta_table, sizeof(double) * p->n_sweeps) == 0)) {
         *out = e.d_thr;
         *owned = false;
         return ISING_OK;
@@ -190,7 +192,9 @@ int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t
       (void)hipFree(d);
       return fail_hip(e, "threshold table upload");
     }
-    g->thr_cache.push_back(ThrCacheEntry{p->schedule, p->n_sweeps, kmax, b0, b1, th, d});
+    std::vector<double> table;
+    if (p->schedule == ISING_SCHED_TABLE) table.assign(p->beta_table, p->beta_table + p->n_sweeps);
+    g->thr_cache.push_back(ThrCacheEntry{p->schedule, p->n_sweeps, kmax, b0, b1, th, std::move(table), d});
     *out = d;
     *owned = false;
     return ISING_OK;

@@ -14,7 +14,8 @@ struct ThrCacheEntry {
   int32_t schedule, n_sweeps, kmax;
   double beta0, beta1;
   uint64_t table_hash;
-  uint32_t* d_thr;  // device [n_sweeps][kmax]
+  std::vector<double> table;  // the beta table of a table schedule (compared on a hit)
+  uint32_t* d_thr;            // device [n_sweeps][kmax]
 };
 
 struct ising_graph {

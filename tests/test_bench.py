@@ -16,14 +16,21 @@ import bench  # noqa: E402
 
 
 def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
+    """A record counts while its sources hash to the recorded value and stops
+    counting once any of them changes."""
+    import hashlib
+
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     key = next(iter(rec))
     kernel, workload = key.split("/")
+    h = hashlib.sha256()
     for f in rec[key]["sources"]:
         os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
         shutil.copy(os.path.join(ROOT, f), tmp_path / f)
+        h.update(open(tmp_path / f, "rb").read())
+    rec[key]["sources_sha256"] = h.hexdigest()  # as recorded when the counters were taken on these sources
     os.makedirs(tmp_path / "profiles")
-    shutil.copy(os.path.join(ROOT, "profiles", "traffic.json"), tmp_path / "profiles" / "traffic.json")
+    json.dump(rec, open(tmp_path / "profiles" / "traffic.json", "w"))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     want = rec[key]["fetch_bytes"] + rec[key]["write_bytes"]
     assert bench.measured_traffic(kernel, workload) == pytest.approx(want)
