@@ -161,14 +161,21 @@ template <int LEV, bool PT>
 __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t Lx, uint32_t q, uint32_t t,
                                           uint32_t quad, const QuadThr& th, uint32_t T1, uint32_t T2,
                                           uint32_t T3, uint32_t& c1, uint32_t& c2, uint32_t& c3) {
+  // sites 3 and 2, then 1 and 0: two Philox blocks in lockstep, shifted in
+  // site 3 (1) before site 2 (0)
 #pragma unroll
-  for (int j = 3; j >= 0; --j) {
-    const uint32_t ci = ci0 + (uint32_t)j * Lx + (q ^ (uint32_t)(j & 1));
-    const u32x4 r = philox_lane_c0(seed, ci, t, quad, kTagMetropolis);
-    if (PT)
-      lt_shift_in4<LEV>(c1, c2, c3, r.v, th.T[0], th.T[1], th.T[2]);
-    else
-      lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
+  for (int j = 3; j >= 1; j -= 2) {
+    const uint32_t cia = ci0 + (uint32_t)j * Lx + (q ^ 1u);
+    const uint32_t cib = ci0 + (uint32_t)(j - 1) * Lx + q;
+    u32x4 ra, rb;
+    philox_lane_c0_x2(seed, cia, cib, t, quad, kTagMetropolis, ra, rb);
+    if (PT) {
+      lt_shift_in4<LEV>(c1, c2, c3, ra.v, th.T[0], th.T[1], th.T[2]);
+      lt_shift_in4<LEV>(c1, c2, c3, rb.v, th.T[0], th.T[1], th.T[2]);
+    } else {
+      lt_shift_in4<LEV>(c1, c2, c3, ra.v, T1, T2, T3);
+      lt_shift_in4<LEV>(c1, c2, c3, rb.v, T1, T2, T3);
+    }
   }
 }
 
