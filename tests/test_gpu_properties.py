@@ -1,0 +1,100 @@
+"""Properties of whole GPU runs at the workloads' full sizes, where the oracle
+would take too long to follow every replica (sampled replicas are compared
+with it in test_gpu_parity.py):
+
+* gauge covariance: with w'_ab = g_a g_b w_ab and s' = g s (g_i = +/-1) every
+  energy change, hence every decision and draw, is unchanged, so the whole
+  trajectory on (w', g s0) is g times the trajectory on (w, s0), with equal
+  energies and flip counts (eq. (2) is invariant under the gauge);
+* the planted instance w_ab = g_a g_b: g times the checkerboard satisfies every
+  bond, so H >= -|E| and cut <= #(w = +1) for every state, with equality
+  exactly at +/- g times the checkerboard (eq. (1), eq. (2))."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import inputs
+
+pytestmark = pytest.mark.gpu
+
+WORKLOADS = [(inputs.TORUS_100x100_R1024, "bs4"), (inputs.TORUS_100x200_R8192, "bp32")]
+IDS = ["torus100x100_bs4", "torus100x200_bp32"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2505_18508_amd as ising
+
+    ising.lib()
+    return torch.device("cuda:0")
+
+
+def _run(wl, weights, spins0, layout):
+    """The workload's whole schedule in one launch; spins0 None: Philox initial state."""
+    import torch
+
+    import paper_2505_18508_amd as ising
+
+    g = ising.create_graph(wl["dims"], 0, weights)
+    R, n = wl["R"], g.n
+    if spins0 is None:
+        spins = torch.zeros((R, n), dtype=torch.int8, device="cuda")
+    else:
+        spins = torch.from_numpy(np.ascontiguousarray(spins0)).cuda()
+    cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+    en = torch.zeros(R, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(R, dtype=torch.int32, device="cuda")
+    ising.run_trials(g, spins, wl["seed"], wl["S"], 0, wl["S"], wl["schedule"], wl["beta0"], wl["beta1"], None,
+                     spins0 is None, layout, cut, en, fl)
+    torch.cuda.synchronize()
+    g.close()
+    return spins.cpu().numpy(), cut.cpu().numpy(), en.cpu().numpy(), fl.cpu().numpy()
+
+
+def _gauge(dims, seed):
+    n = oracle.n_sites(dims)
+    g = inputs.random_spins(seed, 1, n)[0]
+    a, b = oracle.torus_edges(dims)
+    return g, a, b
+
+
+@pytest.mark.parametrize("wl,layout", WORKLOADS, ids=IDS)
+def test_gauge_covariance_of_whole_runs(dev, wl, layout):
+    dims = wl["dims"]
+    n = oracle.n_sites(dims)
+    g, a, b = _gauge(dims, 5)
+    w = inputs.random_weights(wl["weight_seed"], len(dims) * n)
+    wg = (g[a].astype(np.int16) * g[b] * w).astype(np.int8)
+    s0 = inputs.random_spins(wl["seed"], wl["R"], n)
+    s1, c1, e1, f1 = _run(wl, w, s0, layout)
+    s2, c2, e2, f2 = _run(wl, wg, s0 * g, layout)
+    assert (s2 == s1 * g).all()
+    assert (e2 == e1).all() and (f2 == f1).all()
+    assert (c1 == (int(w.sum()) - e1) // 2).all() and (c2 == (int(wg.sum()) - e2) // 2).all()
+    assert (s1 != s0).any() and f1.min() > 0
+
+
+@pytest.mark.parametrize("wl,layout", WORKLOADS, ids=IDS)
+def test_planted_instance_bound_and_optimum(dev, wl, layout):
+    dims = wl["dims"]
+    n = oracle.n_sites(dims)
+    n_edges = len(dims) * n
+    g, a, b = _gauge(dims, 7)
+    w = (g[a].astype(np.int16) * g[b]).astype(np.int8)
+    positive = int((w > 0).sum())
+    spins, cut, en, _ = _run(wl, w, None, layout)
+    assert (cut <= positive).all() and (en >= -n_edges).all()
+    assert (cut == (int(w.sum()) - en) // 2).all()
+    at_bound = np.flatnonzero(en == -n_edges)
+    print("%s: %d of %d replicas at the planted optimum; lowest energies %s" % (
+        layout, len(at_bound), wl["R"], np.sort(en)[:5].tolist()))
+    assert len(at_bound) >= wl["R"] // 10  # seeded runs: 816 of 1,024 and 4,785 of 8,192 get there
+    assert (cut[at_bound] == positive).all()
+    # exactly the two states +/- g * checkerboard
+    board = np.where(oracle.colours(dims) == 0, 1, -1).astype(np.int8)
+    for r in at_bound[:64]:
+        t = spins[r] * g * board
+        assert (t == t[0]).all()

@@ -219,7 +219,7 @@ def test_paper_pairs_fix_single_count_energy():
 # --------------------------------------------------------------------------
 # Brute force and its closed forms
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("dims", [[2, 2], [2, 4], [4, 4], [2, 2, 2], [2, 2, 4]])
+@pytest.mark.parametrize("dims", [[2, 2], [2, 4], [4, 4], [2, 8], [2, 2, 2], [2, 2, 4]])
 def test_bruteforce_closed_forms(dims):
     ne = len(dims) * oracle.n_sites(dims)
     best, state = oracle.maxcut_bruteforce(dims, np.ones(ne, np.int8))
@@ -250,7 +250,7 @@ def test_bruteforce_2x2_is_doubled_four_cycle():
         assert oracle.cut_energy([2, 2], w.astype(np.int8), state)[0][0] == best
 
 
-@pytest.mark.parametrize("dims", [[2, 2], [2, 4], [4, 2], [4, 4], [2, 6], [2, 2, 2], [2, 2, 4]])
+@pytest.mark.parametrize("dims", [[2, 2], [2, 4], [4, 2], [4, 4], [2, 6], [2, 8], [2, 2, 2], [2, 2, 4]])
 def test_annealer_reaches_bruteforce_max(dims):
     ne = len(dims) * oracle.n_sites(dims)
     for seed in range(1, 21):
