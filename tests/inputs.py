@@ -10,6 +10,11 @@ import numpy as np
 TORUS_50x100_R16 = dict(dims=[50, 100], weight_seed=1, seed=101, R=16, S=1000, schedule="linear", beta0=0.1, beta1=3.0)
 TORUS_100x100_R1024 = dict(dims=[100, 100], weight_seed=2, seed=102, R=1024, S=10000, schedule="geometric", beta0=0.05, beta1=4.0)
 TORUS_100x200_R8192 = dict(dims=[100, 200], weight_seed=81, seed=201, R=8192, S=40000, schedule="geometric", beta0=0.05, beta1=4.0)
+# lattices too large for a block's LDS, streamed from HBM
+TORUS_1000x1000_R256 = dict(dims=[1000, 1000], weight_seed=1000, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
+                            beta1=4.0)
+TORUS_64x64x64_R256 = dict(dims=[64, 64, 64], weight_seed=643, seed=7, R=256, S=2000, schedule="geometric", beta0=0.05,
+                           beta1=4.0)
 
 
 def random_spins(seed, n_replicas, n):
