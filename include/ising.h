@@ -358,7 +358,8 @@ int ising_mlp_loss_grad(const float* params, const float* x, const int32_t* idx,
 
 /* One Adam step (Kingma & Ba) on n parameters, step = 1, 2, ...:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
- * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  Asynchronous. */
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  0 <= n <= 2^31 - 1,
+ * else ISING_E_ARG.  Asynchronous. */
 int ising_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step,
                     float lr, float beta1, float beta2, float eps, void* stream);
 
@@ -394,11 +395,13 @@ int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, in
  * predicted final cut / |E| = cut now / |E| + gain, where
  * cut now / |E| = (W_total / |E| - features[r][0]) / 2 (eq. (1)-(2)).
  *   gain      device float [R] (network output);  features device float [R][16].
- *   score     device float [R] (may alias gain).  Asynchronous. */
+ *   score     device float [R] (may alias gain).  0 <= R <= 2^31 - 1, else
+ * ISING_E_ARG.  Asynchronous. */
 int ising_final_cut_score(const ising_graph* g, const float* gain, const float* features, int64_t n_replicas,
                           float* score, void* stream);
 
-/* score[r] = -energy[r] (the energy-ranked baseline of culling). */
+/* score[r] = -energy[r] (the energy-ranked baseline of culling);
+ * 0 <= n_replicas <= 2^31 - 1, else ISING_E_ARG.  Asynchronous. */
 int ising_energy_score(const int64_t* energy, int64_t n_replicas, float* score, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -531,7 +531,7 @@ int ising_mlp_loss_grad(const float* params, const float* x, const int32_t* idx,
 
 int ising_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step, float lr, float beta1,
                     float beta2, float eps, void* stream) {
-  if (n < 0) return fail(ISING_E_ARG, "n < 0");
+  if (n < 0 || n > INT32_MAX) return fail(ISING_E_ARG, "n out of range");
   if (n == 0) return ISING_OK;
   if (!params || !grad || !m || !v) return fail(ISING_E_ARG, "NULL buffer");
   if (step < 1) return fail(ISING_E_ARG, "step must be >= 1");
@@ -607,7 +607,7 @@ int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, in
 int ising_final_cut_score(const ising_graph* g, const float* gain, const float* features, int64_t n_replicas,
                           float* score, void* stream) {
   if (!g) return fail(ISING_E_ARG, "graph is NULL");
-  if (n_replicas < 0) return fail(ISING_E_ARG, "n_replicas < 0");
+  if (n_replicas < 0 || n_replicas > INT32_MAX) return fail(ISING_E_ARG, "n_replicas out of range");
   if (n_replicas == 0) return ISING_OK;
   if (!gain || !features || !score) return fail(ISING_E_ARG, "NULL buffer");
   const double w_over_e = (double)g->w_total / (double)g->n_edges;
@@ -618,7 +618,7 @@ int ising_final_cut_score(const ising_graph* g, const float* gain, const float* 
 }
 
 int ising_energy_score(const int64_t* energy, int64_t n_replicas, float* score, void* stream) {
-  if (n_replicas < 0) return fail(ISING_E_ARG, "n_replicas < 0");
+  if (n_replicas < 0 || n_replicas > INT32_MAX) return fail(ISING_E_ARG, "n_replicas out of range");
   if (n_replicas == 0) return ISING_OK;
   if (!energy || !score) return fail(ISING_E_ARG, "NULL buffer");
   hipLaunchKernelGGL(ising::k_energy_score, dim3((unsigned)((n_replicas + 255) / 256)), dim3(256), 0,

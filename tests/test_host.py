@@ -90,6 +90,12 @@ def test_host_argument_errors():
     assert ising.lib().ising_create_graph(2, d.ctypes.data, 1, None, ctypes.byref(h)) == ising.E_TOPOLOGY
     assert ising.lib().ising_create_graph(2, None, 1, None, ctypes.byref(h)) == ising.E_ARG
     ising.lib().ising_destroy_graph(None)  # NULL-safe
+    # sizes beyond a launch's grid are rejected before any device work
+    L, big = ising.lib(), 2**31
+    fake = ctypes.c_void_p(16)  # never dereferenced: the size check comes first
+    assert L.ising_adam_step(fake, fake, fake, fake, big, 1, 1e-3, 0.9, 0.999, 1e-8, None) == ising.E_ARG
+    assert L.ising_energy_score(fake, big, fake, None) == ising.E_ARG
+    assert L.ising_adam_step(fake, fake, fake, fake, -1, 1, 1e-3, 0.9, 0.999, 1e-8, None) == ising.E_ARG
 
 
 def test_one_hip_runtime_in_the_process():
