@@ -54,6 +54,22 @@ __device__ __forceinline__ void count_bonds(const uint32_t* x, uint32_t& u0, uin
   }
 }
 
+// One stage of a 32 x 32 bit transpose across the 32 lanes of a half-wave
+// (row = lane, column = bit), the partner being lane ^ J: a lane whose bit J
+// is clear keeps the low J-bit half of every 2J-bit block and takes the
+// partner's low halves into its high halves; a lane whose bit J is set keeps
+// its high halves and takes the partner's high halves into its low halves.
+// m = the low halves of the 2J-bit blocks.  After the stages J = 16, 8, 4,
+// 2, 1, bit k of lane j holds what bit j of lane k held.
+template <int J>
+__device__ __forceinline__ uint32_t transpose_stage(uint32_t x, uint32_t lane, uint32_t m) {
+  const uint32_t y = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (J << 10));  // lane ^ J within 32
+  const uint32_t lo = (x & m) | ((y << J) & ~m);
+  const uint32_t hi = (x & ~m) | ((y >> J) & m);
+  const uint32_t upper = 0u - ((lane / (uint32_t)J) & 1u);  // all ones where lane bit J is set
+  return (hi & upper) | (lo & ~upper);                    // select without a branch
+}
+
 template <int NDIM, bool STATS>
 __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a, int p, int t) {
   constexpr int DEG = 2 * NDIM;
@@ -152,21 +168,26 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
       a.spart[((size_t)g * gridDim.x + blockIdx.x) * 2 + threadIdx.x] += c;
     }
   }
-  // flips per replica: a ballot per replica bit gives each wave's count; the
-  // block adds its waves and keeps a running total in its own slot (the
-  // same block index owns the same slot in every launch: no atomics)
+  // flips per replica: transposing the 32 x 32 bit matrix of each half-wave
+  // (row = lane, column = replica bit of F) leaves in lane j the half-wave's
+  // flips of replica j as the bits of one word; the block adds its
+  // half-waves and keeps a running total in its own slot (the same block
+  // index owns the same slot in every launch: no atomics)
   if (a.part) {
-    __shared__ uint32_t wc[kStreamBlock / 64][32];
-    const int wave = threadIdx.x >> 6;
-    for (int j = 0; j < 32; ++j) {
-      const uint32_t c = (uint32_t)__popcll(__ballot((F >> j) & 1u));
-      if ((threadIdx.x & 63) == 0) wc[wave][j] = c;
-    }
+    __shared__ uint32_t wc[kStreamBlock / 32][32];
+    const uint32_t lane = threadIdx.x & 31u;
+    uint32_t x = F;
+    x = transpose_stage<16>(x, lane, 0x0000FFFFu);
+    x = transpose_stage<8>(x, lane, 0x00FF00FFu);
+    x = transpose_stage<4>(x, lane, 0x0F0F0F0Fu);
+    x = transpose_stage<2>(x, lane, 0x33333333u);
+    x = transpose_stage<1>(x, lane, 0x55555555u);
+    wc[threadIdx.x >> 5][lane] = (uint32_t)__popc(x);
     __syncthreads();
     if (threadIdx.x < 32) {
       uint32_t c = 0u;
 #pragma unroll
-      for (int k = 0; k < kStreamBlock / 64; ++k) c += wc[k][threadIdx.x];
+      for (int k = 0; k < kStreamBlock / 32; ++k) c += wc[k][threadIdx.x];
       uint32_t* slot = a.part + ((size_t)g * gridDim.x + blockIdx.x) * 32 + threadIdx.x;
       *slot += c;
     }
