@@ -87,19 +87,23 @@ def batch_layout(ising, g, run):
         return "i8"
 
 
-def cpu_baseline(budget_s):
-    """The oracle on the host's cores: full schedules of the first replicas,
-    one replica per task, until the time budget is spent.  Runs before the
-    GPU is touched; worker processes are spawned fresh."""
+def cpu_baseline(budget_s, wl, task_s=None):
+    """The oracle on the host's cores: the first replicas of workload wl, one
+    replica per task, until the time budget is spent -- each over the whole
+    schedule, or over its first sweeps where one replica's whole schedule
+    would take longer than task_s (default the budget; about 1e8 attempts
+    per core and second).  Runs before the GPU is touched; worker
+    processes are spawned fresh."""
     import concurrent.futures
     import multiprocessing
 
     import oracle
 
-    n = WORKLOAD["dims"][0] * WORKLOAD["dims"][1]
-    w = oracle.random_weights(WORKLOAD["weight_seed"], 2 * n)
+    n = math.prod(wl["dims"])
+    w = oracle.random_weights(wl["weight_seed"], len(wl["dims"]) * n)
     cores = min(os.cpu_count() or 1, 16)
-    S = WORKLOAD["S"]
+    S = wl["S"]
+    end = min(S, max(1, int((budget_s if task_s is None else task_s) * 1e8 / n)))
 
     t0 = time.perf_counter()
     done = []
@@ -107,28 +111,50 @@ def cpu_baseline(budget_s):
     with concurrent.futures.ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
         futs = []
         r = 0
-        while r < min(cores, WORKLOAD["R"]):
-            futs.append(ex.submit(_oracle_one, r, w, WORKLOAD))
+        while r < min(cores, wl["R"]):
+            futs.append(ex.submit(_oracle_one, r, w, wl, end))
             r += 1
         while futs:
             f = futs.pop(0)
             rr, spins = f.result()
             done.append((rr, spins))
-            if time.perf_counter() - t0 < budget_s and r < WORKLOAD["R"]:
-                futs.append(ex.submit(_oracle_one, r, w, WORKLOAD))
+            if time.perf_counter() - t0 < budget_s and r < wl["R"]:
+                futs.append(ex.submit(_oracle_one, r, w, wl, end))
                 r += 1
     elapsed = time.perf_counter() - t0
-    attempts = len(done) * n * S
+    attempts = len(done) * n * end
+    what = "full %d-sweep schedule" % S if end == S else "sweeps [0, %d) of the %d-sweep schedule" % (end, S)
     return {"value": attempts / elapsed, "unit": "attempts/s", "cores": cores, "kind": "oracle",
-            "sample": "%d replicas x full %d-sweep schedule of the same workload (%.1f s)" % (len(done), S, elapsed)}, done
+            "sample": "%d replicas x %s of %s (%.1f s)" % (len(done), what, wl.get("sample_of", "the same workload"),
+                                                          elapsed)}, (done if end == S else None)
 
 
-def _oracle_one(r, w, wl):
+def _oracle_one(r, w, wl, end):
     import oracle
 
-    s, _ = oracle.run(wl["dims"], w, wl["seed"], 1, wl["S"], schedule=oracle.SCHED_GEOMETRIC,
+    s, _ = oracle.run(wl["dims"], w, wl["seed"], 1, wl["S"], 0, end, schedule=oracle.SCHED_GEOMETRIC,
                       beta0=wl["beta0"], beta1=wl["beta1"], replica_begin=r)
     return r, s[0]
+
+
+def cpu_workload(name):
+    """The single-instance workload the oracle baseline samples: the workload
+    itself, or for the batch its largest instance (whose final spins the
+    batch returns)."""
+    W = WORKLOADS[name]
+    if name != "batch4tori":
+        return W
+    dims, wseed, seed, R, S = W["instances"][-1]
+    return dict(dims=dims, weight_seed=wseed, seed=seed, R=R, S=S, schedule=W["schedule"], beta0=W["beta0"],
+                beta1=W["beta1"], sample_of="the batch's %dx%d instance" % tuple(dims))
+
+
+def with_parity(cpu, cpu_spins, final):
+    """The baseline record, with whether the oracle's full-schedule replicas
+    equal the GPU's final spins (None when it ran a window only)."""
+    cpu = dict(cpu)
+    cpu["parity_with_gpu"] = None if cpu_spins is None else all(bool((final[rr] == s).all()) for rr, s in cpu_spins)
+    return cpu
 
 
 def bench_batch(args, ising, metrics, torch, dev):
@@ -187,8 +213,9 @@ def bench_batch(args, ising, metrics, torch, dev):
                      "draws": draws, "draw_fraction": draws / attempts},
         "readout": {"best_cut_per_instance": bests},
     }
+    final = runs[-1]["spins"].cpu().numpy()  # the largest instance, which the oracle baseline samples
     batch.close()
-    return out
+    return out, final
 
 
 def main():
@@ -206,16 +233,14 @@ def main():
     args = ap.parse_args()
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]
-    if args.workload in ("batch4tori", "torus1000x1000", "torus64x64x64"):
-        args.no_cpu = True  # the oracle baseline is measured on the single-instance on-chip workloads
     if args.gpus != 1:
         print("bench.py measures one GPU only: the replica-parallel path has no cross-GPU step to time "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    cpu = None
+    cpu = cpu_spins = None
     if not args.no_cpu:
-        cpu, cpu_spins = cpu_baseline(args.cpu_seconds)
+        cpu, cpu_spins = cpu_baseline(args.cpu_seconds, cpu_workload(args.workload))
 
     import torch
 
@@ -233,7 +258,10 @@ def main():
         del src, dst
     W = WORKLOAD
     if args.workload == "batch4tori":
-        print(json.dumps(bench_batch(args, ising, metrics, torch, dev)))
+        out, final = bench_batch(args, ising, metrics, torch, dev)
+        if cpu is not None:
+            out["cpu_baseline"] = with_parity(cpu, cpu_spins, final)
+        print(json.dumps(out))
         return
     g = ising.create_graph(W["dims"], W["weight_seed"])
     R, S, n = W["R"], W["S"], g.n
@@ -315,9 +343,7 @@ def main():
         out["hbm"] = {"algorithmic_bytes": hbm, "achieved_GBps": hbm / avg_kernel_s / 1e9,
                       "peak_GBps": HBM_PEAK / 1e9, "frac": hbm / avg_kernel_s / HBM_PEAK}
     if cpu is not None:
-        final = spins.cpu().numpy()
-        cpu["parity_with_gpu"] = all(bool((final[rr] == s).all()) for rr, s in cpu_spins)
-        out["cpu_baseline"] = cpu
+        out["cpu_baseline"] = with_parity(cpu, cpu_spins, spins.cpu().numpy())
     g.close()
     print(json.dumps(out))
 

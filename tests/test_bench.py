@@ -70,11 +70,31 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in out.stderr
 
 
-def test_cpu_baseline_times_the_oracle(monkeypatch):
-    wl = dict(bench.WORKLOAD, dims=[8, 8], R=3, S=40)
-    monkeypatch.setattr(bench, "WORKLOAD", wl)
-    res, done = bench.cpu_baseline(0.0)
+def test_cpu_baseline_times_the_oracle():
+    wl = dict(bench.WORKLOADS["torus100x100"], dims=[8, 8], R=3, S=40)
+    res, done = bench.cpu_baseline(0.0, wl, task_s=10.0)
     assert res["kind"] == "oracle" and res["unit"] == "attempts/s" and res["value"] > 0
     assert res["cores"] == min(os.cpu_count() or 1, 16)
+    assert "full 40-sweep schedule" in res["sample"]
     assert sorted(r for r, _ in done) == list(range(min(3, res["cores"])))
     assert all(s.shape == (64,) and set(s.tolist()) <= {-1, 1} for _, s in done)
+    # the oracle's replicas are the same trajectories as a run of all of them
+    import oracle
+
+    w = oracle.random_weights(wl["weight_seed"], 2 * 64)
+    ref, _ = oracle.run(wl["dims"], w, wl["seed"], 3, 40, schedule=oracle.SCHED_GEOMETRIC, beta0=wl["beta0"],
+                        beta1=wl["beta1"])
+    assert bench.with_parity(res, done, ref)["parity_with_gpu"] is True
+
+
+def test_cpu_baseline_windows_large_lattices_and_samples_the_batch():
+    """A lattice too large for one replica's whole schedule within half the
+    budget runs the first sweeps (no parity claim); 3-D lattices take ndim n
+    edges; the batch samples its largest instance."""
+    wl = dict(bench.WORKLOADS["torus64x64x64"], dims=[4, 4, 6], R=2, S=30)
+    res, done = bench.cpu_baseline(0.0, wl, task_s=96 * 10 / 1e8)  # one task's time covers 10 sweeps of 96 sites
+    assert "sweeps [0, 10) of the 30-sweep schedule" in res["sample"] and done is None
+    assert bench.with_parity(res, done, None)["parity_with_gpu"] is None
+    b = bench.cpu_workload("batch4tori")
+    assert b["dims"] == [100, 200] and b["S"] == 20000 and b["R"] == 4096 and "100x200 instance" in b["sample_of"]
+    assert bench.cpu_workload("torus100x100") is bench.WORKLOADS["torus100x100"]
