@@ -142,3 +142,41 @@ def tuned_run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None
                layout, cut, energy, flips, bt, stream=stream)
     return layout, bt
 
+
+
+def main(argv=None):
+    """Time every candidate launch shape of one torus and replica count and
+    print them with the pick and the library's default (AUTO) choice."""
+    import argparse
+
+    import torch
+
+    from . import create_graph, select_layout
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--dims", required=True, help="torus, e.g. 100x100 or 16x16x16")
+    ap.add_argument("--weight-seed", type=int, default=1)
+    ap.add_argument("--replicas", type=int, required=True)
+    ap.add_argument("--sweeps", type=int, default=10000, help="schedule length (geometric 0.05 -> 4.0)")
+    ap.add_argument("--window", type=int, default=200, help="sweeps [0, window) timed per candidate")
+    ap.add_argument("--out", default=None, help="also write the table as JSON")
+    args = ap.parse_args(argv)
+    assert torch.cuda.is_available(), "the tuner times kernels on a GPU"
+    dims = [int(x) for x in args.dims.split("x")]
+    g = create_graph(dims, args.weight_seed)
+    rows = []
+    layout, bt = tune(g, args.replicas, n_sweeps=args.sweeps, window=args.window, use_cache=False,
+                      log=lambda s: (print(s, flush=True), rows.append(s.split())))
+    auto = select_layout(g, args.replicas, args.sweeps)
+    print("pick: %s block %d; default (AUTO): %s" % (layout, bt, auto))
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump({"dims": dims, "replicas": args.replicas, "sweeps": args.sweeps, "window": args.window,
+                       "pick": [layout, bt], "auto": auto,
+                       "candidates": [[r[0], int(r[2].rstrip(":")), float(r[3]), float(r[5])] for r in rows]},
+                      fh, indent=1)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()
