@@ -240,10 +240,12 @@ def test_block_size_does_not_change_results(dev, bt, layout):
         assert (x == y).all()
 
 
-@pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180]), ("bs4", [172, 172])])
+@pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180]), ("bs4", [172, 172]),
+                                          ("bs4", [170, 172]), ("bs4", [12, 30, 56])])
 def test_largest_on_chip_torus(dev, layout, dims):
     # i8: 40,400 sites = 161,600 B of state + 272 B of tables per block; bp32: 32,400 sites = 162,448 B;
-    # bs4: 29,584 sites = 3,698 records of 44 B = 162,712 B + 64 B
+    # bs4: 29,584 sites = 3,698 records of 44 B = 162,712 B + 64 B; 170 rows (2 mod 4) fill 43 word lines
+    # of 86 records as well, the last of each plane holding two rows; 3-D 12 x 30 x 56: 2,688 records of 60 B
     gpu = run_gpu(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout)
     orc = run_oracle(dims, 4, 4, 5, 20, schedule="geometric", beta0=0.05, beta1=4.0)
     assert_same(gpu, orc)
