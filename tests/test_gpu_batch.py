@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +77,43 @@ def test_small_uneven_batch_matches_single_runs_and_oracle(ising):
     dims, wseed, seed, R, S = SMALL[0][:5]
     n = oracle.n_sites(dims)
     ref, fl = oracle.run(dims, oracle.random_weights(wseed, 2 * n), seed, R, S, schedule=oracle.SCHED_GEOMETRIC,
+                         beta0=0.05, beta1=4.0)
+    assert (runs[0]["spins"].cpu().numpy() == ref).all()
+    assert (runs[0]["flips"].cpu().numpy().astype(np.uint32) == fl).all()
+    b.close()
+
+
+SMALL_3D = [([4, 6, 8], 21, 31, 9, 300, 0, 300, "geometric", 0.05, 4.0),   # Ly = 2 mod 4: short last word line
+            ([6, 4, 6], 22, 32, 4, 200, 50, 200, "linear", 0.1, 3.0),
+            ([8, 8, 8], 23, 33, 13, 150, 0, 150, "geometric", 0.05, 4.0)]
+
+
+def test_3d_uneven_batch_matches_single_runs_and_oracle(ising):
+    import torch
+
+    graphs, runs = make_runs(ising, SMALL_3D)
+    for run in runs[1:2]:  # a window that does not start at sweep 0 takes given spins
+        run["spins"].copy_(torch.from_numpy(inputs.random_spins(8, run["spins"].shape[0], run["spins"].shape[1])))
+        run["init_spins"] = False
+    given = runs[1]["spins"].clone()
+    b = ising.Batch(graphs, runs)
+    b.run()
+    torch.cuda.synchronize()
+    for k, (g, run) in enumerate(zip(graphs, runs)):
+        if k == 1:
+            R = given.shape[0]
+            spins = given.clone()
+            cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+            en = torch.zeros(R, dtype=torch.int64, device="cuda")
+            fl = torch.zeros(R, dtype=torch.int32, device="cuda")
+            ising.run_trials(g, spins, run["seed"], run["n_sweeps"], run["sweep_begin"], run["sweep_end"],
+                             run["schedule"], run["beta0"], run["beta1"], None, False, "i8", cut, en, fl)
+            assert_run_equal(run, (spins, cut, en, fl))
+        else:
+            assert_run_equal(run, single(ising, g, run))
+    dims, wseed, seed, R, S = SMALL_3D[0][:5]
+    n = oracle.n_sites(dims)
+    ref, fl = oracle.run(dims, oracle.random_weights(wseed, 3 * n), seed, R, S, schedule=oracle.SCHED_GEOMETRIC,
                          beta0=0.05, beta1=4.0)
     assert (runs[0]["spins"].cpu().numpy() == ref).all()
     assert (runs[0]["flips"].cpu().numpy().astype(np.uint32) == fl).all()
