@@ -210,6 +210,56 @@ def test_given_spins_and_weights_and_table_schedule(dev, layout):
     assert_same(gpu, orc)
 
 
+# beta at which thresholds vanish: T_k = 0 once 4 k beta > 32 ln 2 (k = 3: 1.85, k = 2: 2.77,
+# k = 1: 5.55); past the last, only dE <= 0 flips remain and no draw is taken
+LEVEL_TABLE = [0.0, 0.4, 1.0, 1.8, 1.9, 2.7, 2.8, 3.5, 5.5, 5.6, 7.0, 12.0]
+
+
+@pytest.mark.parametrize("dims", [[20, 30], [6, 8, 10], [6, 10]])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_threshold_levels_vanishing_and_zero_temperature(dev, layout, dims):
+    n = oracle.n_sites(dims)
+    table = np.array(LEVEL_TABLE * 6)  # back and forth between hot and zero-temperature sweeps
+    s0 = inputs.random_spins(12, 19, n)
+    w = inputs.random_weights(13, len(dims) * n)
+    gpu = run_gpu(dims, 0, 91, 19, len(table), schedule="table", table=table, spins0=s0, weights=w, layout=layout)
+    orc = run_oracle(dims, 0, 91, 19, len(table), schedule="table", table=table, spins0=s0, weights=w)
+    assert_same(gpu, orc)
+    assert oracle.threshold(12.0, 1) == 0 and oracle.threshold(1.9, 3) == 0 and oracle.threshold(1.8, 3) > 0
+
+
+@pytest.mark.parametrize("dims", [[20, 30], [6, 8, 10], [6, 10]])
+@pytest.mark.parametrize("layout", ["bs4", "i8"])
+def test_replica_thresholds_mixing_zero_and_hot_replicas(dev, layout, dims):
+    """Per-replica temperatures where some quads are entirely at zero
+    temperature, some mix vanishing levels, some are hot."""
+    import torch
+
+    from oracle import pt as opt
+
+    ising = _ising()
+    n = oracle.n_sites(dims)
+    betas = [12.0, 12.0, 12.0, 12.0, 0.0, 12.0, 2.8, 1.9, 5.6, 5.5, 0.4, 12.0, 1.0, 1.0, 3.5, 7.0, 0.3]
+    R = len(betas)
+    rep = opt.ladder_thresholds(betas, len(dims))
+    s0 = inputs.random_spins(14, R, n)
+    w = inputs.random_weights(15, len(dims) * n)
+    g = ising.create_graph(dims, 0, w)
+    spins = torch.from_numpy(s0.copy()).cuda()
+    cut = torch.zeros(R, dtype=torch.int64, device="cuda")
+    en = torch.zeros(R, dtype=torch.int64, device="cuda")
+    fl = torch.zeros(R, dtype=torch.int32, device="cuda")
+    ising.run_trials(g, spins, 23, 60, 0, 60, "linear", 0.0, 0.0, None, False, layout, cut, en, fl,
+                     replica_thresholds=torch.from_numpy(rep.astype(np.int32)).cuda())
+    torch.cuda.synchronize()
+    ref, rfl = oracle.run_fixed(dims, w, 23, rep, 0, 60, spins=s0)
+    rc, re_ = oracle.cut_energy(dims, w, ref)
+    assert (spins.cpu().numpy() == ref).all()
+    assert (fl.cpu().numpy().astype(np.uint32) == rfl).all()
+    assert (cut.cpu().numpy() == rc).all() and (en.cpu().numpy() == re_).all()
+    g.close()
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_window_resume_equals_single_run(dev, layout):
     dims = [40, 50]
