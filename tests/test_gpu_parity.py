@@ -260,6 +260,18 @@ def test_replica_thresholds_mixing_zero_and_hot_replicas(dev, layout, dims):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [[10, 12], [4, 6, 8]])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_64bit_seeds_and_large_replica_offsets(dev, layout, dims):
+    """Both key words of Philox come from the run and weight seeds, and the
+    replica quad counter from offsets far beyond the replicas of the run."""
+    seed, wseed, off = 0xFEDCBA9876543210, 0x8000000100000003, 2**30 + 4
+    gpu = run_gpu(dims, wseed, seed, 7, 50, schedule="geometric", beta0=0.05, beta1=4.0, layout=layout,
+                  replica_offset=off)
+    orc = run_oracle(dims, wseed, seed, 7, 50, schedule="geometric", beta0=0.05, beta1=4.0, replica_begin=off)
+    assert_same(gpu, orc)
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_window_resume_equals_single_run(dev, layout):
     dims = [40, 50]
