@@ -150,11 +150,13 @@ def test_standardize_groups_matches_oracle(ising, G, R, C):
     assert (got[:R, C - 1] == 0).all()
 
 
-def test_features_match_oracle_over_two_checkpoints(ising):
+@pytest.mark.parametrize("dims", [[20, 30], [6, 8, 10]])  # 3-D: the +/-6 bins of the s f histogram
+def test_features_match_oracle_over_two_checkpoints(ising, dims):
     import torch
 
-    dims, wseed, seed, R, S = [20, 30], 3, 11, 12, 300
-    n, E = 600, 1200
+    wseed, seed, R, S = 3, 11, 12, 300
+    n = oracle.n_sites(dims)
+    E = len(dims) * n
     g = ising.create_graph(dims, wseed)
     w = oracle.random_weights(wseed, E)
     spins = torch.zeros((R, n), dtype=torch.int8, device="cuda")
