@@ -70,6 +70,8 @@ C_CASES = [
     ("bruteforce_skips_states", "state < ((uint64_t)1 << n)", "state < ((uint64_t)1 << (n - 2))",
      [(pins, "test_bruteforce_closed_forms", ([2, 2],)),
       (pins, "test_bruteforce_2x2_is_doubled_four_cycle", ())]),
+    ("replica_thresholds_of_replica_0", "thr[k] = rep_thr[(int64_t)rr * (deg / 2) + k - 1];", "thr[k] = rep_thr[k - 1];",
+     [(pt_pins, "test_ladders_sample_product_of_boltzmann", ([2, 4], (0.4, 1.0)))]),
     ("bruteforce_counts_uncut_edges", "if (xa != xb) c += w[e];", "if (xa == xb) c += w[e];",
      [(pins, "test_bruteforce_closed_forms", ([2, 2],)),
       (pins, "test_bruteforce_2x2_is_doubled_four_cycle", ())]),
