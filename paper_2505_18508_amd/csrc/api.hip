@@ -494,7 +494,10 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
     rc = threshold_table(g, p, st, &d_thr, &owned);
     if (rc) return rc;
   }
-  const ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
+  ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
+  if (layout == ISING_LAYOUT_BS4 && s.block_threads == 0)
+    s.block_threads = ising::sweep_bs4_default_block(g->lat, p->n_replicas, device_info(g->device).cus,
+                                                     device_info(g->device).lds_per_block);
   hipError_t e;
   if (layout == ISING_LAYOUT_STREAM) {
     // stream-ordered working state: the words of every 32-replica group and their input flags

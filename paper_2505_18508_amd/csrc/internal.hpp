@@ -102,6 +102,10 @@ size_t sweep_bs4_dyn_lds(const Lattice& L);
 int sweep_i8_block(const Lattice& L, int requested);
 int sweep_bp32_block(const Lattice& L, int requested);
 int sweep_bs4_block(const Lattice& L, int requested);
+// The bs4 block size a run of n_replicas takes when none is requested: the
+// largest, or about 512 threads where four or more replica quads share a CU
+// and two blocks fit its LDS.
+int sweep_bs4_default_block(const Lattice& L, int n_replicas, int cus, size_t lds_per_cu);
 // The 4 x 4 bit-sliced kernel needs Ly (the second-fastest axis) divisible by 4.
 bool sweep_bs4_supported(const Lattice& L);
 

@@ -50,6 +50,17 @@ int sweep_bs4_block(const Lattice& L, int requested) {
   return lp * L.hx;
 }
 
+int sweep_bs4_default_block(const Lattice& L, int n_replicas, int cus, size_t lds_per_cu) {
+  const int full = sweep_bs4_block(L, 0);
+  const int quads = (n_replicas + 3) / 4;
+  if (full <= 0 || quads < 4 * cus || 2 * sweep_bs4_lds_bytes(L) > lds_per_cu) return full;
+  // four or more quads per compute unit: blocks of at most 512 threads (8
+  // waves, so that four blocks fit the CU's 32 wave slots), whose co-resident
+  // blocks overlap each other's barriers better than the largest block does
+  const int lp = 512 / L.hx;
+  return sweep_bs4_block(L, (lp < 1 ? 1 : lp) * L.hx);
+}
+
 hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStream_t stream) {
   const Lattice& L = g->lat;
   const int block = sweep_bs4_block(L, s.block_threads);

@@ -302,6 +302,22 @@ def test_block_size_does_not_change_results(dev, bt, layout):
         assert (x == y).all()
 
 
+@pytest.mark.parametrize("dims", [[48, 100], [80, 80]])
+def test_bs4_default_block_with_many_quads_per_cu(dev, dims):
+    """4,096 replicas (four quads per CU): the default bs4 block shrinks to at
+    most 512 threads; results equal the largest block's and the oracle's."""
+    R, S = 4096, 20
+    hx = dims[1] // 2
+    full = min(1024 // hx, (dims[0] + 3) // 4) * hx
+    got = run_gpu(dims, 3, 17, R, S, schedule="geometric", beta0=0.05, beta1=4.0, layout="bs4")
+    ref = run_gpu(dims, 3, 17, R, S, schedule="geometric", beta0=0.05, beta1=4.0, layout="bs4", block_threads=full)
+    for x, y in zip(ref, got):
+        assert (x == y).all()
+    for r0 in (0, 1000, 4088):
+        orc = run_oracle(dims, 3, 17, 8, S, schedule="geometric", beta0=0.05, beta1=4.0, replica_begin=r0)
+        assert_same(got, orc, rows=slice(r0, r0 + 8))
+
+
 @pytest.mark.parametrize("layout,dims", [("i8", [200, 202]), ("bp32", [180, 180]), ("bs4", [172, 172]),
                                           ("bs4", [170, 172]), ("bs4", [12, 30, 56])])
 def test_largest_on_chip_torus(dev, layout, dims):
