@@ -72,6 +72,65 @@ def test_init_range_and_uniformity():
     assert (learn.init_params(5) == theta).all() and (learn.init_params(6) != theta).any()
 
 
+@pytest.mark.parametrize("seed", [5, 17, 2024])
+def test_init_bound_of_each_layer_follows_its_own_fan_in(seed):
+    """Kaiming-uniform: every weight of a layer with fan-in F is uniform on
+    [-a, a], a = sqrt(6/F) (W1: F = 16, W2 and W3: F = 64).  The largest |w|
+    of m such draws falls below a (1 - d) with probability (1 - d)^m, and the
+    mean |w| is a/2 with standard error a / sqrt(12 m); so a layer drawn with
+    another layer's fan-in misses both bounds by a factor of two."""
+    p = learn.unpack(learn.init_params(seed))
+    for name, fan_in, slack in (("W1", 16, 0.02), ("W2", 64, 0.01), ("W3", 64, 0.15)):
+        a = math.sqrt(6.0 / fan_in)
+        x = np.abs(p[name].reshape(-1))
+        m = x.size
+        assert a * (1 - slack) < x.max() <= a, name
+        assert abs(x.mean() - a / 2) < 5 * a / math.sqrt(12 * m), name
+
+
+def _eq1_cut_and_energy(dims, w, spins):
+    """eq. (1) and eq. (2) by the double sum over i < j of the dense coupling
+    matrix (parallel edges summed)."""
+    a, b = oracle.torus_edges(dims)
+    n = oracle.n_sites(dims)
+    W = np.zeros((n, n), np.int64)
+    for e in range(len(a)):
+        W[a[e], b[e]] += int(w[e])
+        W[b[e], a[e]] += int(w[e])
+    iu = np.triu_indices(n, 1)
+    cuts, ens = [], []
+    for x in spins.astype(np.int64):
+        outer = np.outer(x, x)[iu]
+        cuts.append(0.5 * np.sum(W[iu] * (1 - outer)))
+        ens.append(np.sum(W[iu] * outer))
+    return np.array(cuts), np.array(ens)
+
+
+@pytest.mark.parametrize("dims", [[6, 8], [4, 4, 6]])
+def test_final_cut_score_is_eq1_cut_plus_gain(dims):
+    """The score of the "gain" label is the predicted end-of-trial cut / |E|:
+    with zero gain it is the replica's eq. (1) cut now / |E| (read from
+    feature 0 = H/|E| through H = W_total - 2 cut), and a gain adds to it
+    unchanged."""
+    rng = np.random.default_rng(len(dims))
+    n = oracle.n_sites(dims)
+    E = len(dims) * n
+    w = oracle.random_weights(int(rng.integers(1, 1000)), E)
+    spins = (2 * rng.integers(0, 2, size=(9, n)) - 1).astype(np.int8)
+    cut, en = _eq1_cut_and_energy(dims, w, spins)
+    f = learn.features(dims, w, spins, en, np.zeros(9, np.uint32), learn.new_track(9), 10, 10, 20, 0.5, 2)
+    zero = learn.final_cut_score(int(w.sum()), E, np.zeros(9), f)
+    assert np.allclose(zero, cut / E, rtol=0, atol=1e-12)
+    gain = rng.standard_normal(9)
+    assert np.allclose(learn.final_cut_score(int(w.sum()), E, gain, f), cut / E + gain, rtol=0, atol=1e-12)
+    # the all-positive torus in its checkerboard state cuts every edge: score 1
+    ones = np.ones(E, np.int8)
+    board = np.where(oracle.colours(dims) == 0, 1, -1).astype(np.int8)[None, :]
+    _, hb = _eq1_cut_and_energy(dims, ones, board)
+    fb = learn.features(dims, ones, board, hb, np.zeros(1, np.uint32), learn.new_track(1), 10, 10, 10, 1.0, 1)
+    assert learn.final_cut_score(E, E, np.zeros(1), fb)[0] == 1.0
+
+
 @pytest.mark.parametrize("dims", [[6, 8], [4, 4, 6]])
 def test_features_identities(dims):
     n = oracle.n_sites(dims)

@@ -101,6 +101,16 @@ PY_CASES = [
       (learn_pins, "test_features_bipartite_closed_form", ())]),
     ("learn", "energy_change_sign", "(H - h_prev) / E", "(h_prev - H) / E",
      [(learn_pins, "test_features_identities", ([6, 8],))]),
+    ("learn", "init_fan_in_of_rows", 'fan_in = shape[-1] if name != "W3" else NH', 'fan_in = shape[0] if name != "W3" else NH',
+     [(learn_pins, "test_init_bound_of_each_layer_follows_its_own_fan_in", (5,))]),
+    ("learn", "init_last_layer_fan_in", 'fan_in = shape[-1] if name != "W3" else NH', 'fan_in = shape[-1] if name != "W3" else NF',
+     [(learn_pins, "test_init_bound_of_each_layer_follows_its_own_fan_in", (5,))]),
+    ("learn", "final_score_energy_sign", "0.5 * (w_total / n_edges - np.asarray", "0.5 * (w_total / n_edges + np.asarray",
+     [(learn_pins, "test_final_cut_score_is_eq1_cut_plus_gain", ([6, 8],))]),
+    ("learn", "final_score_drops_half", "return 0.5 * (w_total / n_edges", "return 1.0 * (w_total / n_edges",
+     [(learn_pins, "test_final_cut_score_is_eq1_cut_plus_gain", ([6, 8],))]),
+    ("learn", "final_score_gain_sign", "[:, 0]) + np.asarray(gain", "[:, 0]) - np.asarray(gain",
+     [(learn_pins, "test_final_cut_score_is_eq1_cut_plus_gain", ([6, 8],))]),
     ("learn", "cull_ranks_worst_first", "(0, -s)", "(0, s)",
      [(learn_pins, "test_cull_order_and_clone", ())]),
     ("learn", "clone_direction", "spins[dst] = spins[src]", "spins[src] = spins[dst]",
