@@ -1,14 +1,15 @@
 """Benchmark: spin-update attempts per second of replica-parallel checkerboard
 Metropolis annealing on one MI355X.
 
-Workload (default): 2-D toroidal grid 100 x 100 (10,000 spins, 20,000 +/-1
-edges from weight seed 2), 1,024 replicas, 10,000 sweeps, geometric beta
-0.05 -> 4.0, run seed 102.  One step = one whole pass of the hot path over
-that batch: Philox initial state, the full sweep schedule with flip counters,
-exact cut/energy, and the host readout (best cut, success probability,
-repetitions r of eq. (3), sweeps-to-target of eq. (4)).  The library picks
-the packing (for this replica count: 4 replicas x 4 sites bit-sliced per
-LDS word); --layout forces another.
+Workload (default): 2-D toroidal grid 100 x 200 (20,000 spins, 40,000 +/-1
+edges from weight seed 81: the size of the paper's largest instance, G81),
+8,192 replicas, 40,000 sweeps, geometric beta 0.05 -> 4.0, run seed 201.
+One step = one whole pass of the hot path over that batch: Philox initial
+state, the full sweep schedule with flip counters, exact cut/energy, and the
+host readout (best cut, success probability, repetitions r of eq. (3),
+sweeps-to-target of eq. (4)).  The library picks the packing (for this
+replica count: 32 replicas per LDS word, one block per 32 replicas);
+--layout forces another.
 
 Prints one JSON line.  Inputs are synthetic (the paper's Gset instances are
 not available); the instance is generated from its seed on the host.
@@ -49,7 +50,24 @@ HBM_PEAK = 8e12
 # streamed layout: per sweep each 32-replica word is read and written once and
 # its neighbours' words read once: 12 bytes per word per sweep
 STREAM_BYTES_PER_WORD_SWEEP = 12
-WORKLOAD = WORKLOADS["torus100x100"]
+DEFAULT_WORKLOAD = "torus100x200"
+WORKLOAD = WORKLOADS[DEFAULT_WORKLOAD]
+# LDS: 256 CUs x 128 bytes per cycle x 2.4 GHz
+LDS_PEAK = 256 * 128 * 2.4e9
+
+
+def lds_bytes_per_attempt(layout, ndim):
+    """Algorithmic LDS bytes per attempt of the on-chip packings: bp32 reads
+    a site's word and its 2 ndim neighbours' words and writes it back (4 B
+    each) per 32 attempts; bs4 (2-D) reads ten 4-byte record entries per
+    16-attempt word.  None where no such figure is derived."""
+    if layout == "bp32":
+        return (2 * ndim + 2) * 4 / 32
+    if layout == "bs4" and ndim == 2:
+        return 10 * 4 / 16
+    return None
+
+
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU issue
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # algorithmic VALU lane-ops: one Philox4x32-10 word per attempt that needs a
@@ -227,7 +245,7 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="torus100x100")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default=DEFAULT_WORKLOAD)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a reference kernel of known traffic for counters)")
     args = ap.parse_args()
@@ -337,6 +355,10 @@ def main():
                      "draw_fraction": draws / attempts},
         "readout": {"best_cut": results[-1][0], "target": target, "P_s": p_s, "r": r, "STT_sweeps": S * r},
     }
+    lds_b = lds_bytes_per_attempt(layout, len(W["dims"]))
+    if lds_b is not None:
+        out["lds"] = {"algorithmic_bytes_per_attempt": lds_b, "achieved_TBps": lds_b * attempts / avg_kernel_s / 1e12,
+                      "peak_TBps": LDS_PEAK / 1e12, "frac": lds_b * attempts / avg_kernel_s / LDS_PEAK}
     if streamed:
         # kernel_ms covers the whole launch sequence (pack, 2 S half-sweeps, unpack, cut)
         hbm = STREAM_BYTES_PER_WORD_SWEEP * n * groups * S

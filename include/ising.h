@@ -63,7 +63,7 @@ enum { ISING_SCHED_LINEAR = 0, ISING_SCHED_GEOMETRIC = 1, ISING_SCHED_TABLE = 2 
 
 /* Internal packing of the replicas; results do not depend on it. */
 enum {
-  ISING_LAYOUT_AUTO = 0,  /* library chooses (autotuned where a tuning exists)  */
+  ISING_LAYOUT_AUTO = 0,  /* library chooses by a fixed rule (ising_select_layout) */
   ISING_LAYOUT_I8 = 1,    /* 4 replicas per 32-bit word: spin + maintained field */
   ISING_LAYOUT_BP32 = 2,  /* 32 replicas per 32-bit word: one spin bit each      */
   ISING_LAYOUT_STREAM = 3, /* 32 replicas per word, state in HBM, one launch per */
@@ -130,7 +130,8 @@ typedef struct {
                              /* geometric: beta0*(beta1/beta0)^(t/(S-1)), both > 0;  */
                              /* S == 1 gives beta0                                   */
   const double* beta_table;  /* host double[S], every entry >= 0, when TABLE         */
-  int32_t block_threads;     /* 0: library default / tuned; else threads per block   */
+  int32_t block_threads;     /* 0: the library's rule; else threads per block (the   */
+                             /* autotuner's pick, for instance)                      */
                              /* (rounded to the kernel's granularity)                */
   int32_t replica_offset;    /* global id of replica 0 of this call (Philox streams */
                              /* are keyed by global ids); a multiple of 4; normally 0 */
@@ -337,24 +338,30 @@ int ising_mlp_init(uint64_t seed, float* params, void* stream);
 
 /* y[b] = W3 relu(W2 relu(W1 z_b + b1) + b2) + b3 with z_b = (x_b - mean) / std
  * (mean, std: device float[16], or both NULL for z = x).
- * x device float [B][16] (rows idx[b] when idx != NULL: device int32 [B]);
- * y device float [B].  Asynchronous. */
-int ising_mlp_forward(const float* params, const float* x, const int32_t* idx, const float* mean,
-                      const float* std, int64_t batch, float* y, void* stream);
+ *   x       device float [x_rows][16]; sample b reads row idx[b] when idx !=
+ *           NULL (device int32 [B]), else row b (then B <= x_rows, else
+ *           ISING_E_ARG).  A sample whose idx[b] lies outside [0, x_rows)
+ *           reads nothing and gets y[b] = NaN.
+ *   y       device float [B].  Asynchronous. */
+int ising_mlp_forward(const float* params, const float* x, int64_t x_rows, const int32_t* idx,
+                      const float* mean, const float* std, int64_t batch, float* y, void* stream);
 
 /* Floats of workspace ising_mlp_loss_grad needs for a batch. */
 int64_t ising_mlp_workspace_floats(int64_t batch);
 
 /* Mean squared error L = (1/B) sum_b (y_b - target_b)^2 of the forward pass
  * above and its gradient with respect to every parameter.
- *   target    device float [B] (entries idx[b] when idx != NULL).
+ *   x, x_rows, idx  as for ising_mlp_forward; a sample whose idx[b] lies
+ *             outside [0, x_rows) reads neither x nor target and makes the
+ *             loss and the gradient NaN.
+ *   target    device float [B], or [x_rows] read at idx[b] when idx != NULL.
  *   grad      device float [ISING_MLP_PARAMS] (overwritten).
  *   loss      device float [1] (overwritten), or NULL.
  *   workspace device float [ising_mlp_workspace_floats(B)].
  * Summation order is fixed, so results are reproducible.  Asynchronous. */
-int ising_mlp_loss_grad(const float* params, const float* x, const int32_t* idx, const float* mean,
-                        const float* std, const float* target, int64_t batch, float* grad,
-                        float* loss, float* workspace, void* stream);
+int ising_mlp_loss_grad(const float* params, const float* x, int64_t x_rows, const int32_t* idx,
+                        const float* mean, const float* std, const float* target, int64_t batch,
+                        float* grad, float* loss, float* workspace, void* stream);
 
 /* One Adam step (Kingma & Ba) on n parameters, step = 1, 2, ...:
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

@@ -98,9 +98,9 @@ def lib():
         f32 = ctypes.c_float
         L.ising_features.argtypes = [vp, vp, vp, vp, i64, vp, i32, i32, i32, ctypes.c_double, i32, vp, vp]
         L.ising_mlp_init.argtypes = [u64, vp, vp]
-        L.ising_mlp_forward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.ising_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp, i64, vp, vp]
         L.ising_mlp_workspace_floats.argtypes = [i64]
-        L.ising_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.ising_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp]
         L.ising_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, f32, f32, f32, f32, vp]
         L.ising_feature_stats.argtypes = [vp, i64, vp, vp, vp]
         L.ising_cull_clone.argtypes = [vp, i64, i64, vp, vp, vp, vp]
@@ -143,19 +143,32 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _dev(t, name, dtypes, numel=None):
-    """_ptr after checking that t has one of dtypes (torch dtype names) and at
+def _want(t, name, dtypes, numel=None):
+    """Check that t (or None) has one of dtypes (torch dtype names) and at
     least numel elements: the kernels index these buffers by the sizes the
     call states, so a short or mistyped buffer is refused here."""
     if t is None:
-        return None
+        return
     import torch
 
     if t.dtype not in tuple(getattr(torch, d) for d in dtypes):
         raise ValueError("%s must be %s, got %s" % (name, " or ".join(dtypes), str(t.dtype).replace("torch.", "")))
     if numel is not None and t.numel() < numel:
         raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+
+
+def _dev(t, name, dtypes, numel=None):
+    """_ptr after _want's checks."""
+    _want(t, name, dtypes, numel)
     return _ptr(t)
+
+
+def _devs(*specs):
+    """Device pointers of several (tensor, name, dtypes, numel) buffers, every
+    one checked before any is converted."""
+    for spec in specs:
+        _want(*spec)
+    return [_ptr(spec[0]) for spec in specs]
 
 
 I32 = ("int32", "uint32")
@@ -337,14 +350,43 @@ def features(graph, spins, energy, window_flips, track, sweeps_done, window, n_s
                                 _dev(out, "features", ("float32",), R * N_FEATURES), _stream(stream)))
 
 
+F32 = ("float32",)
+
+
+def _rows16(x, name="x"):
+    """Rows of a float32 [rows][16] feature table."""
+    if x.dim() != 2 or x.shape[1] != N_FEATURES:
+        raise ValueError("%s must be [rows][%d]" % (name, N_FEATURES))
+    return x.shape[0]
+
+
+def _batch(x, idx, batch, mean, std):
+    """Rows of x and samples B of a forward/backward call.  idx is int32
+    [>= B]; without idx the batch must lie within x.  Index values outside
+    x are the kernels' concern (they read nothing and give NaN)."""
+    rows = _rows16(x)
+    B = (idx.shape[0] if idx is not None else rows) if batch is None else int(batch)
+    if B < 0:
+        raise ValueError("batch must be >= 0")
+    if idx is None and B > rows:
+        raise ValueError("batch %d exceeds the %d rows of x" % (B, rows))
+    if (mean is None) != (std is None):
+        raise ValueError("mean and std must both be given or both be None")
+    return rows, B
+
+
 def mlp_init(seed, params, stream=None):
-    _check(lib().ising_mlp_init(int(seed), _ptr(params), _stream(stream)))
+    """Kaiming-uniform parameters from Philox: params float32 [5313]."""
+    (pp,) = _devs((params, "params", F32, MLP_PARAMS))
+    _check(lib().ising_mlp_init(int(seed), pp, _stream(stream)))
 
 
 def mlp_forward(params, x, y, idx=None, mean=None, std=None, batch=None, stream=None):
-    B = (idx.shape[0] if idx is not None else x.shape[0]) if batch is None else int(batch)
-    _check(lib().ising_mlp_forward(_ptr(params), _ptr(x), _ptr(idx), _ptr(mean), _ptr(std), B, _ptr(y),
-                                   _stream(stream)))
+    """y[b] = network(x[idx[b]]) (or x[b]): x float32 [rows][16], y float32 [B]."""
+    rows, B = _batch(x, idx, batch, mean, std)
+    pp, xp, ip, mp, sp, yp = _devs((params, "params", F32, MLP_PARAMS), (x, "x", F32), (idx, "idx", ("int32",), B),
+                                   (mean, "mean", F32, N_FEATURES), (std, "std", F32, N_FEATURES), (y, "y", F32, B))
+    _check(lib().ising_mlp_forward(pp, xp, rows, ip, mp, sp, B, yp, _stream(stream)))
 
 
 def mlp_workspace_floats(batch):
@@ -353,19 +395,33 @@ def mlp_workspace_floats(batch):
 
 def mlp_loss_grad(params, x, target, grad, workspace, loss=None, idx=None, mean=None, std=None, batch=None,
                   stream=None):
-    B = (idx.shape[0] if idx is not None else x.shape[0]) if batch is None else int(batch)
-    _check(lib().ising_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(idx), _ptr(mean), _ptr(std), _ptr(target), B,
-                                     _ptr(grad), _ptr(loss), _ptr(workspace), _stream(stream)))
+    """Mean squared error of the batch and its gradient: target float32
+    [rows] (read at idx) or [B]; grad float32 [5313]; loss float32 [1] or
+    None; workspace float32 [mlp_workspace_floats(B)]."""
+    rows, B = _batch(x, idx, batch, mean, std)
+    pp, xp, ip, mp, sp, tp, gp, lp, wp = _devs(
+        (params, "params", F32, MLP_PARAMS), (x, "x", F32), (idx, "idx", ("int32",), B),
+        (mean, "mean", F32, N_FEATURES), (std, "std", F32, N_FEATURES),
+        (target, "target", F32, rows if idx is not None else B), (grad, "grad", F32, MLP_PARAMS),
+        (loss, "loss", F32, 1), (workspace, "workspace", F32, mlp_workspace_floats(B)))
+    _check(lib().ising_mlp_loss_grad(pp, xp, rows, ip, mp, sp, tp, B, gp, lp, wp, _stream(stream)))
 
 
 def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-    _check(lib().ising_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), int(step), float(lr),
-                                 float(beta1), float(beta2), float(eps), _stream(stream)))
+    """One Adam step on every element of params (float32); grad, m, v alike."""
+    n = params.numel()
+    pp, gp, mp, vp = _devs((params, "params", F32), (grad, "grad", F32, n), (m, "m", F32, n), (v, "v", F32, n))
+    _check(lib().ising_adam_step(pp, gp, mp, vp, n, int(step), float(lr), float(beta1), float(beta2), float(eps),
+                                 _stream(stream)))
 
 
 def feature_stats(x, mean, std, rows=None, stream=None):
-    n = x.shape[0] if rows is None else int(rows)
-    _check(lib().ising_feature_stats(_ptr(x), n, _ptr(mean), _ptr(std), _stream(stream)))
+    """Column means and deviations of x float32 [rows][16] into mean, std float32 [16]."""
+    n = _rows16(x) if rows is None else int(rows)
+    if n > x.shape[0]:
+        raise ValueError("rows %d exceeds the %d rows of x" % (n, x.shape[0]))
+    xp, mp, sp = _devs((x, "x", F32), (mean, "mean", F32, N_FEATURES), (std, "std", F32, N_FEATURES))
+    _check(lib().ising_feature_stats(xp, n, mp, sp, _stream(stream)))
 
 
 def cull_clone(score, spins, track=None, order=None, stream=None):

@@ -158,9 +158,50 @@ uint64_t fnv1a(const void* data, size_t bytes) {
 
 constexpr size_t kMaxCachedTables = 64;
 
+bool same_schedule(const ThrCacheEntry& e, const ising_run_params* p, int kmax, double b0, double b1, uint64_t th) {
+  return e.schedule == p->schedule && e.n_sweeps == p->n_sweeps && e.kmax == kmax && e.beta0 == b0 &&
+         e.beta1 == b1 && e.table_hash == th &&
+         (p->schedule != ISING_SCHED_TABLE ||
+          std::memcmp(e.table.data(), p->beta_table, sizeof(double) * p->n_sweeps) == 0);
+}
+
+// A cached table is usable on `stream` once its upload has completed; a
+// stream other than the uploading one waits for that upload's event while it
+// is still in flight (a batch plan, made synchronously, waits on the host).
+// Called with the graph's lock held.
+int use_cached(const ThrCacheEntry& e, hipStream_t stream, bool for_plan, uint32_t** out, bool* owned) {
+  if (for_plan) {
+    hipError_t err = hipEventSynchronize(e.ready);
+    if (err != hipSuccess) return fail_hip(err, "threshold table upload");
+  } else if (stream != e.made_on && hipEventQuery(e.ready) == hipErrorNotReady) {
+    hipError_t err = hipStreamWaitEvent(stream, e.ready, 0);
+    if (err != hipSuccess) return fail_hip(err, "threshold table wait");
+  }
+  *out = e.d_thr;
+  *owned = false;
+  return ISING_OK;
+}
+
+// Release the host sources of finished uncached uploads.  Lock held.
+void reap_uploads(const ising_graph* g) {
+  auto& v = g->thr_uploads;
+  for (size_t i = 0; i < v.size();) {
+    if (hipEventQuery(v[i].done) == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    (void)hipEventDestroy(v[i].done);
+    v[i] = std::move(v.back());
+    v.pop_back();
+  }
+}
+
 // Device threshold table of p's whole schedule, cached on the graph.  Cached
 // tables are immutable and freed with the graph; beyond the cache size a
-// stream-ordered allocation is made and released after the launch.
+// stream-ordered allocation is made and released after the launch.  No path
+// but a batch plan's (for_plan: synchronous, as batch creation is) waits for
+// the device: uploads are asynchronous on `stream` from host copies that live
+// until the copy has completed.
 int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t stream, uint32_t** out,
                     bool* owned, bool for_plan = false) {
   const int kmax = g->degree / 2;
@@ -170,35 +211,15 @@ int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t
   {
     std::lock_guard<std::mutex> lock(g->mu);
     for (const ThrCacheEntry& e : g->thr_cache)
-      if (e.schedule == p->schedule && e.n_sweeps == p->n_sweeps && e.kmax == kmax && e.beta0 == b0 &&
-          e.beta1 == b1 && e.table_hash == th &&
-          (p->schedule != ISING_SCHED_TABLE ||
-           std::memcmp(e.table.data(), p->beta_table, sizeof(double) * p->n_sweeps) == 0)) {
-        *out = e.d_thr;
-        *owned = false;
-        return ISING_OK;
-      }
+      if (same_schedule(e, p, kmax, b0, b1, th)) return use_cached(e, stream, for_plan, out, owned);
   }
   std::vector<uint32_t> host((size_t)p->n_sweeps * kmax);
   fill_thresholds(p, kmax, host.data());
   const size_t bytes = host.size() * sizeof(uint32_t);
   std::lock_guard<std::mutex> lock(g->mu);
-  if (g->thr_cache.size() < kMaxCachedTables) {
-    uint32_t* d = nullptr;
-    hipError_t e = hipMalloc(&d, bytes);
-    if (e != hipSuccess) return fail(ISING_E_NOMEM, "threshold table (%zu bytes): %s", bytes, hipGetErrorString(e));
-    e = hipMemcpy(d, host.data(), bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(d);
-      return fail_hip(e, "threshold table upload");
-    }
-    std::vector<double> table;
-    if (p->schedule == ISING_SCHED_TABLE) table.assign(p->beta_table, p->beta_table + p->n_sweeps);
-    g->thr_cache.push_back(ThrCacheEntry{p->schedule, p->n_sweeps, kmax, b0, b1, th, std::move(table), d});
-    *out = d;
-    *owned = false;
-    return ISING_OK;
-  }
+  for (const ThrCacheEntry& e : g->thr_cache)  // another thread may have added it meanwhile
+    if (same_schedule(e, p, kmax, b0, b1, th)) return use_cached(e, stream, for_plan, out, owned);
+  reap_uploads(g);
   uint32_t* d = nullptr;
   if (for_plan) {  // kept by a batch plan and freed with it
     hipError_t e = hipMalloc(&d, bytes);
@@ -212,16 +233,32 @@ int threshold_table(const ising_graph* g, const ising_run_params* p, hipStream_t
     *owned = true;
     return ISING_OK;
   }
-  hipError_t e = hipMallocAsync((void**)&d, bytes, stream);
+  const bool cache = g->thr_cache.size() < kMaxCachedTables;
+  hipError_t e = cache ? hipMalloc(&d, bytes) : hipMallocAsync((void**)&d, bytes, stream);
   if (e != hipSuccess) return fail(ISING_E_NOMEM, "threshold table (%zu bytes): %s", bytes, hipGetErrorString(e));
-  e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host buffer is released on return
+  hipEvent_t ev = nullptr;
+  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, host.data(), bytes, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipEventRecord(ev, stream);
   if (e != hipSuccess) {
-    (void)hipFreeAsync(d, stream);
+    // the copy may be in flight: wait for the stream before the host source goes
+    (void)hipStreamSynchronize(stream);
+    if (ev) (void)hipEventDestroy(ev);
+    if (cache) (void)hipFree(d);
+    else (void)hipFreeAsync(d, stream);
     return fail_hip(e, "threshold table upload");
   }
+  if (cache) {
+    std::vector<double> table;
+    if (p->schedule == ISING_SCHED_TABLE) table.assign(p->beta_table, p->beta_table + p->n_sweeps);
+    g->thr_cache.push_back(ThrCacheEntry{p->schedule, p->n_sweeps, kmax, b0, b1, th, std::move(table),
+                                         std::move(host), d, ev, stream});
+    *owned = false;
+  } else {
+    g->thr_uploads.push_back(ThrUpload{std::move(host), ev});
+    *owned = true;
+  }
   *out = d;
-  *owned = true;
   return ISING_OK;
 }
 
@@ -339,7 +376,14 @@ void ising_destroy_graph(ising_graph* g) {
   if (!g) return;
   (void)hipFree(g->d_w);
   (void)hipFree(g->d_wbits);
-  for (ThrCacheEntry& e : g->thr_cache) (void)hipFree(e.d_thr);
+  for (ThrCacheEntry& e : g->thr_cache) {
+    (void)hipFree(e.d_thr);  // waits for the device, uploads included
+    (void)hipEventDestroy(e.ready);
+  }
+  for (ThrUpload& u : g->thr_uploads) {
+    (void)hipEventSynchronize(u.done);
+    (void)hipEventDestroy(u.done);
+  }
   delete g;
 }
 

@@ -15,7 +15,17 @@ struct ThrCacheEntry {
   double beta0, beta1;
   uint64_t table_hash;
   std::vector<double> table;  // the beta table of a table schedule (compared on a hit)
+  std::vector<uint32_t> host; // source of the upload (kept: the copy is asynchronous)
   uint32_t* d_thr;            // device [n_sweeps][kmax]
+  hipEvent_t ready;           // recorded after the upload, on the stream that made it
+  hipStream_t made_on;
+};
+
+// Host source of an uncached table's asynchronous upload, released once its
+// event has completed.
+struct ThrUpload {
+  std::vector<uint32_t> host;
+  hipEvent_t done;
 };
 
 struct ising_graph {
@@ -30,6 +40,7 @@ struct ising_graph {
   uint8_t* d_wbits = nullptr;  // device per-site weight sign bits, colour-split order [n]
   mutable std::mutex mu;
   mutable std::vector<ThrCacheEntry> thr_cache;
+  mutable std::vector<ThrUpload> thr_uploads;
 };
 
 namespace ising {

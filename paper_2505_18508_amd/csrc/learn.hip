@@ -132,25 +132,37 @@ __device__ __forceinline__ void load_params(float* sp, const float* params) {
   for (int k = threadIdx.x; k < P; k += blockDim.x) sp[k] = params[k];
 }
 
-__device__ __forceinline__ void load_input(float* z, const float* x, const int32_t* idx, int64_t b, const float* mean,
-                                           const float* sd) {
+// Row b of the batch: x row idx[b] (or b).  A row index outside [0, x_rows)
+// reads nothing: z is zero and the caller makes that sample's outputs NaN.
+__device__ __forceinline__ bool load_input(float* z, const float* x, int64_t x_rows, const int32_t* idx, int64_t b,
+                                           const float* mean, const float* sd) {
   const int64_t row = idx ? (int64_t)idx[b] : b;
+  if (row < 0 || row >= x_rows) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) z[k] = 0.0f;
+    return false;
+  }
   const float* xr = x + row * NF;
 #pragma unroll
   for (int k = 0; k < NF; ++k) z[k] = mean ? (xr[k] - mean[k]) / sd[k] : xr[k];
+  return true;
 }
 
 constexpr int kFwdBlock = 256;
 
-__global__ void __launch_bounds__(kFwdBlock) k_mlp_forward(const float* params, const float* x, const int32_t* idx,
-                                                          const float* mean, const float* sd, int64_t batch, float* y) {
+__global__ void __launch_bounds__(kFwdBlock) k_mlp_forward(const float* params, const float* x, int64_t x_rows,
+                                                          const int32_t* idx, const float* mean, const float* sd,
+                                                          int64_t batch, float* y) {
   __shared__ float sp[P];
   load_params(sp, params);
   __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * kFwdBlock + threadIdx.x;
   if (b >= batch) return;
   float z[NF], h1[NH];
-  load_input(z, x, idx, b, mean, sd);
+  if (!load_input(z, x, x_rows, idx, b, mean, sd)) {
+    y[b] = __builtin_nanf("");
+    return;
+  }
   for (int j = 0; j < NH; ++j) {
     float acc = sp[OFF_B1 + j];
 #pragma unroll
@@ -174,9 +186,9 @@ constexpr int kGradChunk = 64;
 constexpr int kRow = P + 1;  // gradient + loss per workspace row
 constexpr int kPad = NH + 1;
 
-__global__ void __launch_bounds__(kGradChunk) k_mlp_grad(const float* params, const float* x, const int32_t* idx,
-                                                        const float* mean, const float* sd, const float* target,
-                                                        int64_t batch, float* ws) {
+__global__ void __launch_bounds__(kGradChunk) k_mlp_grad(const float* params, const float* x, int64_t x_rows,
+                                                        const int32_t* idx, const float* mean, const float* sd,
+                                                        const float* target, int64_t batch, float* ws) {
   extern __shared__ float sm[];
   float* sp = sm;                          // [P]
   float* zs = sp + P;                      // [64][NF]
@@ -197,7 +209,7 @@ __global__ void __launch_bounds__(kGradChunk) k_mlp_grad(const float* params, co
   float* d1 = d1s + s * kPad;
   if (b < batch) {
     float zr[NF];
-    load_input(zr, x, idx, b, mean, sd);
+    const bool valid = load_input(zr, x, x_rows, idx, b, mean, sd);
 #pragma unroll
     for (int k = 0; k < NF; ++k) z[k] = zr[k];
     for (int j = 0; j < NH; ++j) {
@@ -213,8 +225,9 @@ __global__ void __launch_bounds__(kGradChunk) k_mlp_grad(const float* params, co
       h2[j] = fmaxf(acc, 0.0f);
       out = fmaf(sp[OFF_W3 + j], h2[j], out);
     }
-    const float t = idx ? target[idx[b]] : target[b];
-    const float err = out - t;
+    // an out-of-range row makes the loss and the gradient NaN (target not read)
+    const float t = valid ? (idx ? target[idx[b]] : target[b]) : 0.0f;
+    const float err = valid ? out - t : __builtin_nanf("");
     const float dy = 2.0f * err / (float)batch;
     dys[s] = dy;
     les[s] = err * err;
@@ -493,15 +506,17 @@ int ising_mlp_init(uint64_t seed, float* params, void* stream) {
   return e == hipSuccess ? ISING_OK : fail_hip(e, "mlp init launch");
 }
 
-int ising_mlp_forward(const float* params, const float* x, const int32_t* idx, const float* mean, const float* std,
-                      int64_t batch, float* y, void* stream) {
+int ising_mlp_forward(const float* params, const float* x, int64_t x_rows, const int32_t* idx, const float* mean,
+                      const float* std, int64_t batch, float* y, void* stream) {
   if (batch < 0 || batch > ((int64_t)1 << 31)) return fail(ISING_E_ARG, "batch out of range");
+  if (x_rows < 0) return fail(ISING_E_ARG, "x_rows must be >= 0");
+  if (!idx && batch > x_rows) return fail(ISING_E_ARG, "batch exceeds x_rows without idx");
   if (batch == 0) return ISING_OK;
   if (!params || !x || !y) return fail(ISING_E_ARG, "NULL buffer");
   if ((mean == nullptr) != (std == nullptr)) return fail(ISING_E_ARG, "mean and std must both be given or both NULL");
   const int64_t grid = (batch + ising::kFwdBlock - 1) / ising::kFwdBlock;
   hipLaunchKernelGGL(ising::k_mlp_forward, dim3((unsigned)grid), dim3(ising::kFwdBlock), 0, (hipStream_t)stream, params,
-                     x, idx, mean, std, batch, y);
+                     x, x_rows, idx, mean, std, batch, y);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ISING_OK : fail_hip(e, "mlp forward launch");
 }
@@ -511,9 +526,12 @@ int64_t ising_mlp_workspace_floats(int64_t batch) {
   return ((batch + ising::kGradChunk - 1) / ising::kGradChunk) * (int64_t)ising::kRow;
 }
 
-int ising_mlp_loss_grad(const float* params, const float* x, const int32_t* idx, const float* mean, const float* std,
-                        const float* target, int64_t batch, float* grad, float* loss, float* workspace, void* stream) {
+int ising_mlp_loss_grad(const float* params, const float* x, int64_t x_rows, const int32_t* idx, const float* mean,
+                        const float* std, const float* target, int64_t batch, float* grad, float* loss, float* workspace,
+                        void* stream) {
   if (batch < 1 || batch > ((int64_t)1 << 31)) return fail(ISING_E_ARG, "batch out of range");
+  if (x_rows < 0) return fail(ISING_E_ARG, "x_rows must be >= 0");
+  if (!idx && batch > x_rows) return fail(ISING_E_ARG, "batch exceeds x_rows without idx");
   if (!params || !x || !target || !grad || !workspace) return fail(ISING_E_ARG, "NULL buffer");
   if ((mean == nullptr) != (std == nullptr)) return fail(ISING_E_ARG, "mean and std must both be given or both NULL");
   hipStream_t st = (hipStream_t)stream;
@@ -521,8 +539,8 @@ int ising_mlp_loss_grad(const float* params, const float* x, const int32_t* idx,
   const size_t lds = ising::grad_lds_bytes();
   hipError_t e = hipFuncSetAttribute((const void*)ising::k_mlp_grad, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return fail_hip(e, "mlp grad attribute");
-  hipLaunchKernelGGL(ising::k_mlp_grad, dim3((unsigned)nb), dim3(ising::kGradChunk), lds, st, params, x, idx, mean, std,
-                     target, batch, workspace);
+  hipLaunchKernelGGL(ising::k_mlp_grad, dim3((unsigned)nb), dim3(ising::kGradChunk), lds, st, params, x, x_rows, idx, mean,
+                     std, target, batch, workspace);
   hipLaunchKernelGGL(ising::k_mlp_reduce, dim3((ISING_MLP_PARAMS + 1 + 255) / 256), dim3(256), 0, st, workspace, (int)nb,
                      batch, grad, loss);
   e = hipGetLastError();

@@ -177,21 +177,22 @@ def train(X, Y, epochs=20, batch=8192, lr=1e-3, seed=3, log=None, label="final")
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     grad = torch.zeros_like(params)
-    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    starts = list(range(0, N, batch))
+    # one loss slot per step, read back once per epoch (no host sync per step)
+    losses = torch.zeros(len(starts), dtype=torch.float32, device=dev)
     ws = torch.zeros(mlp_workspace_floats(batch), dtype=torch.float32, device=dev)
     rng = np.random.default_rng(seed)
     step = 0
     history = []
     for epoch in range(epochs):
         perm = torch.from_numpy(rng.permutation(N).astype(np.int32)).to(dev)
-        losses = []
-        for start in range(0, N, batch):
+        for k, start in enumerate(starts):
             idx = perm[start:start + batch]
-            mlp_loss_grad(params, X, Y, grad, ws, loss, idx=idx, mean=mean, std=std)
+            mlp_loss_grad(params, X, Y, grad, ws, losses[k:k + 1], idx=idx, mean=mean, std=std)
             step += 1
             adam_step(params, grad, m, v, step, lr=lr)
-            losses.append(loss.item() * idx.shape[0])
-        history.append(sum(losses) / N)
+        sizes = np.array([min(batch, N - s0) for s0 in starts], np.float64)
+        history.append(float((losses.cpu().numpy().astype(np.float64) * sizes).sum() / N))
         if log:
             log("epoch %d loss %.6g" % (epoch, history[-1]))
     return Model(params, mean, std, label), history

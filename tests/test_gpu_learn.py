@@ -82,6 +82,32 @@ def test_mlp_forward_gathers_rows(ising):
     assert torch.equal(y1, y2)
 
 
+def test_mlp_rows_outside_x_read_nothing_and_give_nan(ising):
+    """A gathered row index outside x reads nothing: its forward output is
+    NaN (the other rows are exact), and the loss and gradient of a batch
+    holding it are NaN."""
+    import torch
+
+    rng = np.random.default_rng(5)
+    p = random_params(ising, 8)
+    x = dev_tensor(rng.standard_normal((100, 16)).astype(np.float32))
+    idx_np = np.array([0, 99, 100, -1, 2**31 - 1, -2**31, 7], np.int32)
+    y = torch.zeros(len(idx_np), dtype=torch.float32, device="cuda")
+    ising.mlp_forward(p, x, y, idx=dev_tensor(idx_np))
+    ok = np.array([0, 1, 6])
+    ref = torch.zeros(3, dtype=torch.float32, device="cuda")
+    ising.mlp_forward(p, x[idx_np[ok].astype(np.int64)].contiguous(), ref)
+    got = y.cpu().numpy()
+    assert np.isnan(got[[2, 3, 4, 5]]).all()
+    assert (got[ok] == ref.cpu().numpy()).all()
+    grad = torch.zeros(5313, dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ws = torch.zeros(ising.mlp_workspace_floats(len(idx_np)), dtype=torch.float32, device="cuda")
+    t = torch.zeros(100, dtype=torch.float32, device="cuda")
+    ising.mlp_loss_grad(p, x, t, grad, ws, loss, idx=dev_tensor(idx_np))
+    assert np.isnan(loss.item()) and torch.isnan(grad).any().item()
+
+
 @pytest.mark.parametrize("B", [1, 100, 1000, 8192])
 def test_mlp_loss_grad_matches_oracle(ising, B):
     import torch

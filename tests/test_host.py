@@ -129,3 +129,67 @@ def test_binding_refuses_mistyped_or_short_buffers():
     with pytest.raises(ValueError, match="must be int32 or uint32"):
         ising._dev(torch.zeros(4, dtype=torch.float32), "flips", ising.I32, 4)
     assert ising._dev(None, "cut", ("int64",), 4) is None
+
+
+def test_learned_part_wrappers_check_every_buffer():
+    """mlp_init, mlp_forward, mlp_loss_grad, adam_step and feature_stats
+    refuse a short or mistyped buffer (host tensors here: each check fires
+    before the device-pointer check, so no GPU is needed)."""
+    import torch
+
+    f32 = torch.float32
+    P = ising.MLP_PARAMS
+    with pytest.raises(ValueError, match="params holds 5312 elements, needs 5313"):
+        ising.mlp_init(1, torch.zeros(P - 1, dtype=f32))
+    with pytest.raises(ValueError, match="params must be float32"):
+        ising.mlp_init(1, torch.zeros(P, dtype=torch.float64))
+    p = torch.zeros(P, dtype=f32)
+    x = torch.zeros((8, 16), dtype=f32)
+    with pytest.raises(ValueError, match=r"x must be \[rows\]\[16\]"):
+        ising.mlp_forward(p, torch.zeros((8, 15), dtype=f32), torch.zeros(8, dtype=f32))
+    with pytest.raises(ValueError, match="batch 9 exceeds the 8 rows"):
+        ising.mlp_forward(p, x, torch.zeros(9, dtype=f32), batch=9)
+    with pytest.raises(ValueError, match="idx must be int32"):
+        ising.mlp_forward(p, x, torch.zeros(4, dtype=f32), idx=torch.zeros(4, dtype=torch.int64))
+    with pytest.raises(ValueError, match="mean and std"):
+        ising.mlp_forward(p, x, torch.zeros(8, dtype=f32), mean=torch.zeros(16, dtype=f32))
+    with pytest.raises(ValueError, match="std holds 15"):
+        ising.mlp_forward(p, x, torch.zeros(8, dtype=f32), mean=torch.zeros(16, dtype=f32),
+                          std=torch.zeros(15, dtype=f32))
+    with pytest.raises(ValueError, match="params holds"):
+        ising.mlp_forward(torch.zeros(100, dtype=f32), x, torch.zeros(8, dtype=f32))
+    with pytest.raises(ValueError, match="y holds 7 elements, needs 8"):
+        ising.mlp_forward(p, x, torch.zeros(7, dtype=f32))
+    ws = torch.zeros(ising.mlp_workspace_floats(8), dtype=f32)
+    g = torch.zeros(P, dtype=f32)
+    # with idx the target is read at the gathered rows: it must cover x
+    with pytest.raises(ValueError, match="target holds 4 elements, needs 8"):
+        ising.mlp_loss_grad(p, x, torch.zeros(4, dtype=f32), g, ws, idx=torch.zeros(4, dtype=torch.int32))
+    with pytest.raises(ValueError, match="grad holds"):
+        ising.mlp_loss_grad(p, x, torch.zeros(8, dtype=f32), torch.zeros(10, dtype=f32), ws)
+    with pytest.raises(ValueError, match="workspace holds"):
+        ising.mlp_loss_grad(p, x, torch.zeros(8, dtype=f32), g, ws[:10])
+    with pytest.raises(ValueError, match="loss must be float32"):
+        ising.mlp_loss_grad(p, x, torch.zeros(8, dtype=f32), g, ws, loss=torch.zeros(1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="m holds 10 elements"):
+        ising.adam_step(p, g, torch.zeros(10, dtype=f32), torch.zeros(P, dtype=f32), 1)
+    with pytest.raises(ValueError, match="grad must be float32"):
+        ising.adam_step(p, g.double(), torch.zeros(P, dtype=f32), torch.zeros(P, dtype=f32), 1)
+    with pytest.raises(ValueError, match="mean holds 3"):
+        ising.feature_stats(x, torch.zeros(3, dtype=f32), torch.zeros(16, dtype=f32))
+    with pytest.raises(ValueError, match="rows 9 exceeds"):
+        ising.feature_stats(x, torch.zeros(16, dtype=f32), torch.zeros(16, dtype=f32), rows=9)
+    # every check passed: the last one is the device-pointer check
+    with pytest.raises(ValueError, match="device tensor"):
+        ising.mlp_forward(p, x, torch.zeros(8, dtype=f32))
+
+
+def test_mlp_entry_points_reject_a_batch_beyond_x():
+    """Without idx the C entry points refuse a batch larger than x_rows
+    before any launch (pointers never dereferenced)."""
+    L = ising.lib()
+    fake = ctypes.c_void_p(16)
+    assert L.ising_mlp_forward(fake, fake, 8, None, None, None, 9, fake, None) == ising.E_ARG
+    assert b"x_rows" in L.ising_last_error()
+    assert L.ising_mlp_loss_grad(fake, fake, 8, None, None, None, fake, 9, fake, None, fake, None) == ising.E_ARG
+    assert L.ising_mlp_forward(fake, fake, -1, fake, None, None, 4, fake, None) == ising.E_ARG
