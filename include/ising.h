@@ -170,6 +170,27 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
                      int64_t* cut_out, int64_t* energy_out, uint32_t* flips_out, void* stream);
 
 /*
+ * ising_run_trials for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, layouts and results, bit for bit, but no allocation of
+ * any kind.  The working memory is one fixed 16 MiB array per GPU inside the
+ * library (ISING_NOALLOC_SCRATCH_BYTES), held until the process ends, which
+ * takes the window's acceptance thresholds ((sweep_end - sweep_begin) *
+ * degree/2 uint32) and, for the streamed layout, its HBM state (the words of
+ * every 32-replica group, input flags, flip/RNG counters and, above 65,536
+ * sites, the cut's partial sums).  A run needing more returns
+ * ISING_E_UNSUPPORTED before anything is enqueued.  The thresholds are
+ * carried into the array by small launches' arguments, so nothing on the
+ * host outlives the call.  Every call on one GPU shares that GPU's array:
+ * calls on one stream follow each other safely, calls that overlap on one GPU
+ * (other streams, other threads) race and give undefined results.
+ * Asynchronous on `stream`.
+ */
+#define ISING_NOALLOC_SCRATCH_BYTES (16u << 20)
+int ising_run_trials_noalloc(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout,
+                             int64_t* cut_out, int64_t* energy_out, uint32_t* flips_out, void* stream);
+
+/*
  * The ISING_LAYOUT_* that ising_run_trials would use for g and p (p->layout
  * AUTO resolved), into *layout_out.  Validates g and p as ising_run_trials
  * does (same error codes) and launches nothing; no spins buffer is needed.

@@ -27,7 +27,7 @@ LAYOUTS = {"auto": LAYOUT_AUTO, "i8": LAYOUT_I8, "bp32": LAYOUT_BP32, "stream": 
 
 EXPORTED = [
     "ising_create_graph", "ising_destroy_graph", "ising_graph_info", "ising_graph_weights",
-    "ising_generate_weights", "ising_run_trials", "ising_select_layout", "ising_eval_cut", "ising_thresholds",
+    "ising_generate_weights", "ising_run_trials", "ising_run_trials_noalloc", "ising_select_layout", "ising_eval_cut", "ising_thresholds",
     "ising_philox_dump", "ising_last_error",
     "ising_features", "ising_mlp_init", "ising_mlp_forward", "ising_mlp_workspace_floats", "ising_mlp_loss_grad",
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
@@ -90,6 +90,7 @@ def lib():
         L.ising_graph_weights.argtypes = [vp, vp]
         L.ising_generate_weights.argtypes = [i32, vp, u64, vp]
         L.ising_run_trials.argtypes = [vp, ctypes.POINTER(RunParams), vp, vp, vp, vp, vp]
+        L.ising_run_trials_noalloc.argtypes = [vp, ctypes.POINTER(RunParams), vp, vp, vp, vp, vp]
         L.ising_eval_cut.argtypes = [vp, vp, i64, vp, vp, vp]
         L.ising_thresholds.argtypes = [ctypes.POINTER(RunParams), i32, vp]
         L.ising_philox_dump.argtypes = [u64, vp, i64, vp, vp]
@@ -279,6 +280,23 @@ def run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, sche
     energy int64 [R], flips uint32/int32 [R], stats int64 [2] optional;
     replica_thresholds uint32/int32 [R][degree/2] (each replica at its own
     fixed temperature) optional.  Asynchronous."""
+    _run(lib().ising_run_trials, graph, spins, seed, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1,
+         beta_table, init_spins, layout, cut, energy, flips, block_threads, replica_offset, stats, stream,
+         replica_thresholds)
+
+
+def run_trials_noalloc(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, schedule="linear", beta0=0.1,
+                       beta1=3.0, beta_table=None, init_spins=True, layout="auto", cut=None, energy=None, flips=None,
+                       block_threads=0, replica_offset=0, stats=None, stream=None, replica_thresholds=None):
+    """ising_run_trials_noalloc: run_trials without any allocation (the
+    library's fixed per-GPU scratch; calls overlapping on one GPU race)."""
+    _run(lib().ising_run_trials_noalloc, graph, spins, seed, n_sweeps, sweep_begin, sweep_end, schedule, beta0,
+         beta1, beta_table, init_spins, layout, cut, energy, flips, block_threads, replica_offset, stats, stream,
+         replica_thresholds)
+
+
+def _run(fn, graph, spins, seed, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1, beta_table, init_spins,
+         layout, cut, energy, flips, block_threads, replica_offset, stats, stream, replica_thresholds):
     R = spins.shape[0]
     if spins.dim() != 2 or spins.shape[1] != graph.n:
         raise ValueError("spins must be [R][%d]" % graph.n)
@@ -286,9 +304,8 @@ def run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None, sche
         raise ValueError("replica_thresholds must be [R][%d]" % (graph.degree // 2))
     p, keep = make_params(seed, R, n_sweeps, sweep_begin, sweep_end, schedule, beta0, beta1, beta_table,
                           init_spins, layout, block_threads, replica_offset, stats, replica_thresholds)
-    _check(lib().ising_run_trials(graph.handle, ctypes.byref(p), _dev(spins, "spins", ("int8",)),
-                                  _dev(cut, "cut", ("int64",), R), _dev(energy, "energy", ("int64",), R),
-                                  _dev(flips, "flips", I32, R), _stream(stream)))
+    _check(fn(graph.handle, ctypes.byref(p), _dev(spins, "spins", ("int8",)), _dev(cut, "cut", ("int64",), R),
+              _dev(energy, "energy", ("int64",), R), _dev(flips, "flips", I32, R), _stream(stream)))
     del keep
 
 

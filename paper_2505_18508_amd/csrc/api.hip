@@ -505,6 +505,62 @@ ising::SweepLaunch make_launch(const ising_run_params* p, const uint32_t* d_thr,
   return s;
 }
 
+// The sweep launch of a checked run (layout resolved); the streamed layout
+// takes its working state (words, input flags, counters) from the caller.
+hipError_t dispatch_run(const ising_graph* g, const ising_run_params* p, int layout, ising::SweepLaunch& s,
+                        uint32_t* words, uint32_t* bad, uint32_t* part, hipStream_t st, int64_t* cut_part = nullptr) {
+  if (layout == ISING_LAYOUT_BS4 && s.block_threads == 0)
+    s.block_threads = ising::sweep_bs4_default_block(g->lat, p->n_replicas, device_info(g->device).cus,
+                                                     device_info(g->device).lds_per_block);
+  if (layout == ISING_LAYOUT_STREAM) return ising::launch_sweep_stream(g, s, words, bad, part, st, cut_part);
+  return layout == ISING_LAYOUT_BP32  ? ising::launch_sweep_bp32(g, s, st)
+         : layout == ISING_LAYOUT_BS4 ? ising::launch_sweep_bs4(g, s, st)
+                                      : ising::launch_sweep_i8(g, s, st);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of ising_run_trials_noalloc: a fixed array in device memory (one
+// copy per GPU, held until the process ends).  Host code never uses the
+// array's name as an address: its device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kScratchBytes = ISING_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+constexpr int kFillWords = 960;  // words per fill launch, passed as kernel arguments
+
+struct FillChunk {
+  uint32_t n;
+  uint32_t w[kFillWords];
+};
+
+__global__ void k_fill_words(uint32_t* dst, FillChunk c) {
+  for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) dst[i] = c.w[i];
+}
+
+}  // namespace
+
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / sizeof(uint32_t)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[kScratchDevices];
+
+// Device address of the scratch array on device dev (the current device).
+int scratch_on(int dev, uint32_t** out) {
+  if (dev < 0 || dev >= kScratchDevices) return fail(ISING_E_UNSUPPORTED, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail_hip(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+    g_scratch_ptr[dev] = (uint32_t*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ISING_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
 
 struct ising_batch {
@@ -539,9 +595,6 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
     if (rc) return rc;
   }
   ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
-  if (layout == ISING_LAYOUT_BS4 && s.block_threads == 0)
-    s.block_threads = ising::sweep_bs4_default_block(g->lat, p->n_replicas, device_info(g->device).cus,
-                                                     device_info(g->device).lds_per_block);
   hipError_t e;
   if (layout == ISING_LAYOUT_STREAM) {
     // stream-ordered working state: the words of every 32-replica group and their input flags
@@ -560,16 +613,67 @@ int ising_run_trials(const ising_graph* g, const ising_run_params* p, int8_t* sp
       if (owned) (void)hipFreeAsync(d_thr, st);
       return fail(ISING_E_NOMEM, "streamed state (%zu bytes): %s", wbytes, hipGetErrorString(e));
     }
-    e = ising::launch_sweep_stream(g, s, words, bad, part, st);
+    e = dispatch_run(g, p, layout, s, words, bad, part, st);
     (void)hipFreeAsync(words, st);
     (void)hipFreeAsync(bad, st);
     if (part) (void)hipFreeAsync(part, st);
   } else {
-    e = layout == ISING_LAYOUT_BP32  ? ising::launch_sweep_bp32(g, s, st)
-        : layout == ISING_LAYOUT_BS4 ? ising::launch_sweep_bs4(g, s, st)
-                                     : ising::launch_sweep_i8(g, s, st);
+    e = dispatch_run(g, p, layout, s, nullptr, nullptr, nullptr, st);
   }
   if (owned) (void)hipFreeAsync(d_thr, st);
+  if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");
+  return ISING_OK;
+}
+
+int ising_run_trials_noalloc(const ising_graph* g, const ising_run_params* p, int8_t* spins_inout, int64_t* cut_out,
+                             int64_t* energy_out, uint32_t* flips_out, void* stream) {
+  int layout = 0;
+  int rc = check_run(g, p, spins_inout, &layout);
+  if (rc) return rc;
+  const int kmax = g->degree / 2;
+  const bool per_replica = replica_thr(p) != nullptr;
+  // scratch plan: the window's threshold rows, then (streamed layout) the
+  // words of every 32-replica group, their input flags and counters
+  const size_t rows = per_replica ? 0 : (size_t)(p->sweep_end - p->sweep_begin) * (size_t)kmax;
+  const size_t off_words = round256(rows * sizeof(uint32_t));
+  size_t off_bad = off_words, off_part = off_words, off_cut = off_words, total = off_words;
+  if (layout == ISING_LAYOUT_STREAM) {
+    const size_t groups = ((size_t)p->n_replicas + 31) / 32;
+    off_bad = off_words + round256(ising::stream_words_bytes(g->lat, p->n_replicas));
+    off_part = off_bad + round256(sizeof(uint32_t) * groups);
+    off_cut = off_part + round256(ising::stream_part_bytes(g->lat, p->n_replicas, flips_out != nullptr,
+                                                           p->stats_out != nullptr));
+    total = off_cut + round256(cut_out || energy_out ? ising::cut_part_bytes(g->lat, p->n_replicas) : 0);
+  }
+  if (total > kScratchBytes)
+    return fail(ISING_E_UNSUPPORTED, "this run needs %zu bytes of scratch; ising_run_trials_noalloc has %zu", total,
+                kScratchBytes);
+  uint32_t* base = nullptr;
+  rc = scratch_on(g->device, &base);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t* d_thr = nullptr;
+  if (!per_replica) {
+    // rows t = sweep_begin .. sweep_end-1 of the table ising_thresholds gives,
+    // carried by the fill launches' arguments: nothing on the host outlives the call
+    FillChunk c;
+    for (size_t i0 = 0; i0 < rows; i0 += kFillWords) {
+      c.n = (uint32_t)(rows - i0 < (size_t)kFillWords ? rows - i0 : (size_t)kFillWords);
+      for (uint32_t j = 0; j < c.n; ++j) {
+        const size_t i = i0 + j;
+        const int32_t t = p->sweep_begin + (int32_t)(i / (size_t)kmax);
+        c.w[j] = ising::accept_threshold(schedule_beta(p, t), (int)(i % (size_t)kmax) + 1);
+      }
+      hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(256), 0, st, base + i0, c);
+    }
+    // the sweep kernels read row t at thr + t kmax, t in [sweep_begin, sweep_end)
+    d_thr = (const uint32_t*)((uintptr_t)base - (uintptr_t)p->sweep_begin * (uintptr_t)kmax * sizeof(uint32_t));
+  }
+  ising::SweepLaunch s = make_launch(p, d_thr, spins_inout, cut_out, energy_out, flips_out);
+  uint8_t* b8 = (uint8_t*)base;
+  hipError_t e = dispatch_run(g, p, layout, s, (uint32_t*)(b8 + off_words), (uint32_t*)(b8 + off_bad),
+                              (uint32_t*)(b8 + off_part), st, (int64_t*)(b8 + off_cut));
+  if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return fail_hip(e, "sweep kernel launch");
   return ISING_OK;
 }

@@ -95,18 +95,26 @@ __global__ void k_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint
 
 }  // namespace
 
+size_t cut_part_bytes(const Lattice& L, int64_t n_replicas) {
+  const uint32_t n_chunks = ((uint32_t)L.n + kCutChunk - 1) / kCutChunk;
+  return n_chunks > 1 ? sizeof(int64_t) * 3 * (size_t)n_chunks * (size_t)n_replicas : 0;
+}
+
 hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut,
-                             int64_t* energy, hipStream_t stream) {
+                             int64_t* energy, hipStream_t stream, int64_t* part_scratch) {
   if (n_replicas == 0 || (!cut && !energy)) return hipSuccess;
   // large lattices: several blocks per replica, so that enough loads are in
-  // flight; their sums go through a stream-ordered scratch array
+  // flight; their sums go through the caller's scratch (every entry written
+  // before it is read) or a stream-ordered array
   const uint32_t n = (uint32_t)g->lat.n;
   const uint32_t n_chunks = (n + kCutChunk - 1) / kCutChunk;
   const uint32_t chunk = n_chunks == 1 ? n : kCutChunk;
   if ((int64_t)n_chunks * n_replicas > INT32_MAX) return hipErrorInvalidValue;
   int64_t* part = nullptr;
-  if (n_chunks > 1) {
-    hipError_t e = hipMallocAsync((void**)&part, sizeof(int64_t) * 3 * (size_t)n_chunks * (size_t)n_replicas, stream);
+  const bool own = n_chunks > 1 && !part_scratch;
+  if (n_chunks > 1) part = part_scratch;
+  if (own) {
+    hipError_t e = hipMallocAsync((void**)&part, cut_part_bytes(g->lat, n_replicas), stream);
     if (e != hipSuccess) return e;
   }
   const dim3 grid((unsigned)(n_chunks * n_replicas));
@@ -119,7 +127,7 @@ hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t 
   if (part) {
     hipLaunchKernelGGL(k_cut_finish, dim3((unsigned)((n_replicas + 255) / 256)), dim3(256), 0, stream, part, n_chunks,
                        n_replicas, cut, energy);
-    (void)hipFreeAsync(part, stream);
+    if (own) (void)hipFreeAsync(part, stream);
   }
   return hipGetLastError();
 }

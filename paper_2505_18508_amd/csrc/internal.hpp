@@ -79,10 +79,15 @@ hipError_t launch_sweep_bs4(const ising_graph* g, const SweepLaunch& s, hipStrea
 // part: stream_part_bytes() of per-block flip and RNG counts (needed when s.flips or s.stats).
 size_t stream_words_bytes(const Lattice& L, int n_replicas);
 size_t stream_part_bytes(const Lattice& L, int n_replicas, bool flips, bool stats);
+// cut_part: cut_part_bytes() of scratch for the cut's partial sums, or null
+// (then allocated on the stream when needed).
 hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint32_t* words, uint32_t* bad,
-                               uint32_t* part, hipStream_t stream);
+                               uint32_t* part, hipStream_t stream, int64_t* cut_part = nullptr);
+// Bytes of partial sums launch_cut_energy passes between its two kernels (0:
+// one block per replica, none needed).
+size_t cut_part_bytes(const Lattice& L, int64_t n_replicas);
 hipError_t launch_cut_energy(const ising_graph* g, const int8_t* spins, int64_t n_replicas, int64_t* cut,
-                             int64_t* energy, hipStream_t stream);
+                             int64_t* energy, hipStream_t stream, int64_t* part_scratch = nullptr);
 hipError_t launch_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* out, hipStream_t stream);
 
 // A prepared persistent launch over several instances (four-replica

@@ -310,7 +310,7 @@ size_t stream_part_bytes(const Lattice& L, int n_replicas, bool flips, bool stat
 }
 
 hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint32_t* words, uint32_t* bad,
-                               uint32_t* part, hipStream_t stream) {
+                               uint32_t* part, hipStream_t stream, int64_t* cut_part) {
   const Lattice& L = g->lat;
   const int groups = (s.n_replicas + 31) / 32;
   const int bx = stream_blocks_x(L);
@@ -361,7 +361,7 @@ hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint3
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (s.cut || s.energy) {
-    e = launch_cut_energy(g, s.spins, s.n_replicas, s.cut, s.energy, stream);
+    e = launch_cut_energy(g, s.spins, s.n_replicas, s.cut, s.energy, stream, cut_part);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mark_invalid, dim3((unsigned)((s.n_replicas + 255) / 256)), dim3(256), 0, stream, bad,
                        s.n_replicas, s.cut, s.energy);
