@@ -283,7 +283,11 @@ typedef struct ising_batch ising_batch;
  *   graphs[k], params[k] instance k and its run (layout AUTO, I8 or BS4;
  *                        AUTO takes BS4 where the lattice allows it, else
  *                        I8; stats_out must be NULL; replica_thresholds
- *                        may be given, as for ising_run_trials).
+ *                        may be given, as for ising_run_trials;
+ *                        block_threads > 0 limits the threads of the
+ *                        1,024-thread launch block that work on this
+ *                        instance's items, as it sizes a single run's
+ *                        block, 0 = all of them).
  *   spins[k]             device int8 [R_k][n_k] (in/out, as ising_run_trials).
  *   cut_out, energy_out, flips_out  NULL, or arrays of n_inst device
  *                        pointers (entries may be NULL).

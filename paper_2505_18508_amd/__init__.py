@@ -496,7 +496,7 @@ class Batch:
             p, keep = make_params(run["seed"], spins.shape[0], run["n_sweeps"], run.get("sweep_begin", 0),
                                   run.get("sweep_end"), run.get("schedule", "geometric"), run.get("beta0", 0.05),
                                   run.get("beta1", 4.0), run.get("beta_table"), run.get("init_spins", True),
-                                  run.get("layout", "auto"), 0, run.get("replica_offset", 0),
+                                  run.get("layout", "auto"), run.get("block_threads", 0), run.get("replica_offset", 0),
                                   replica_thresholds=rt)
             params[i] = p
             self._keep.append(keep)

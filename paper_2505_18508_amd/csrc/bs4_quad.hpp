@@ -179,8 +179,10 @@ __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t 
   }
 }
 
-// One half-sweep of colour P over this thread's words.
-template <int NDIM, int P, bool FLIPS, bool STATS, bool PT, bool PART>
+// One half-sweep of colour P over this thread's words, with the first LEV
+// threshold levels nonzero (0: no draws at all).  The word is written back
+// unconditionally: no thread reads a colour-P word during this half-sweep.
+template <int NDIM, int P, int LEV, bool FLIPS, bool STATS, bool PT, bool PART>
 __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4Args& a, int t, uint32_t quad,
                                          const QuadThr& th, uint32_t T1, uint32_t T2, uint32_t T3,
                                          uint32_t valid16, uint32_t* fl, uint32_t& n_blocks,
@@ -209,26 +211,17 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
       k3 = ~(u0 | u1 | u2);
     }
     uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-    // compare levels needed: the largest k with a nonzero T_k
-    const bool l1 = PT ? th.lev != 0 : T1 != 0u;
-    const bool only1 = PT ? th.lev == 1 : T2 == 0u;
-    const bool only2 = NDIM == 2 || (PT ? th.lev == 2 : T3 == 0u);
-    if (l1) {
+    if (LEV > 0) {
       const uint32_t q = ((uint32_t)P + z) & 1u;
-      if (only1)
-        bs4_draws<1, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
-      else if (only2)
-        bs4_draws<2, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
-      else
-        bs4_draws<3, PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
+      bs4_draws<(LEV > 0 ? LEV : 1), PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
       if (STATS) {  // schedule only: per-replica thresholds reject statistics
-        const uint32_t need = (k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & valid16 & rows;
+        const uint32_t need = (k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u)) & valid16 & rows;
         n_blocks += 4u;
         n_draws += __popc(need);
       }
     }
-    const uint32_t F = (acc | (k1 & c1) | (k2 & c2) | (k3 & c3)) & rows;
-    if (F) ((uint32_t*)(lds + base))[P] = s ^ F;
+    const uint32_t F = (acc | (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u)) & rows;
+    ((uint32_t*)(lds + base))[P] = s ^ F;
     if (FLIPS) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) fl[b] += __popc(F & (0x1111u << b));
@@ -247,6 +240,22 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
     else
       ci0 += wk.ci_step;
   }
+}
+
+// bs4_half for the number of nonzero threshold levels of this sweep
+// (the largest k with some T_k != 0; thresholds decrease with k).
+template <int NDIM, int P, bool FLIPS, bool STATS, bool PT, bool PART>
+__device__ __forceinline__ void bs4_half_lev(int lev, char* lds, const Bs4Walk& wk, const Bs4Args& a, int t,
+                                             uint32_t quad, const QuadThr& th, uint32_t T1, uint32_t T2, uint32_t T3,
+                                             uint32_t valid16, uint32_t* fl, uint32_t& n_blocks, uint32_t& n_draws) {
+  if (lev == 0)
+    bs4_half<NDIM, P, 0, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+  else if (lev == 1)
+    bs4_half<NDIM, P, 1, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+  else if (NDIM == 2 || lev == 2)
+    bs4_half<NDIM, P, 2, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+  else
+    bs4_half<NDIM, P, 3, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
 }
 
 // One replica quad (local replicas r0 .. r0+3) for the window of a.  Called
@@ -385,11 +394,14 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
       T2 = tr[1];
       T3 = NDIM == 3 ? tr[2] : 0u;
     }
+    const int lev = PT ? th.lev : T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
     if (active)
-      bs4_half<NDIM, 0, FLIPS, STATS, PT, PART>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+      bs4_half_lev<NDIM, 0, FLIPS, STATS, PT, PART>(lev, lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks,
+                                                    n_draws);
     __syncthreads();
     if (active)
-      bs4_half<NDIM, 1, FLIPS, STATS, PT, PART>(lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+      bs4_half_lev<NDIM, 1, FLIPS, STATS, PT, PART>(lev, lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks,
+                                                    n_draws);
     __syncthreads();
   }
 

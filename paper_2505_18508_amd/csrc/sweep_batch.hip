@@ -94,7 +94,10 @@ hipError_t build_batch(const ising_graph* const* graphs, const SweepLaunch* laun
     BatchInst& I = inst[(size_t)k];
     I.bs4 = layouts[k] == ISING_LAYOUT_BS4 ? 1 : 0;
     I.part = (I.bs4 && L.Ly % 4 != 0) ? 1 : 0;
-    const int block = I.bs4 ? sweep_bs4_block(L, kBatchBlock) : sweep_i8_block(L, kBatchBlock);
+    // threads that work on this instance's items: its requested block size
+    // (the autotuner's pick, say) within the launch's block, else all of it
+    const int want = s.block_threads > 0 && s.block_threads < kBatchBlock ? s.block_threads : kBatchBlock;
+    const int block = I.bs4 ? sweep_bs4_block(L, want) : sweep_i8_block(L, want);
     if (block <= 0) return hipErrorInvalidValue;
     auto fill = [&](auto& a) {
       a.lat = L;

@@ -117,6 +117,159 @@ __device__ __forceinline__ void draw_compare(uint64_t seed, uint32_t ci, uint32_
   }
 }
 
+// Per-thread constants of the walk over a colour's site words: column m of
+// lines line0, line0 + lp, ... (as in the four-replica kernel).
+struct BpWalk {
+  uint32_t m, line0, lp, hx, Lx, Ly, Lz, half, lines;
+  uint32_t lp_y, lp_z, y0, z0;
+  uint32_t d_up, d_dn, row, plane, dyp_wrap, dym_wrap, dzp_wrap, dzm_wrap;
+  uint32_t own_step, ci_step;
+};
+
+// Flip decisions of one site word: x[d] = unsatisfied-bond bits of slot d
+// (any slot order: only their count matters), s = the word.  dE = 2 deg - 4u
+// with u the count: flip when u >= deg/2, else k = deg/2 - u and the replica
+// flips iff its Philox word is below T_k.  LEV = number of nonzero thresholds
+// (they decrease with k, so the nonzero ones are a prefix); 0 draws nothing.
+template <int NDIM, int LEV, bool STATS>
+__device__ __forceinline__ uint32_t bp_decide(const uint32_t* x, uint64_t seed, uint32_t ci, uint32_t t, uint32_t quad0,
+                                              uint32_t T1, uint32_t T2, uint32_t T3, uint32_t valid_lanes,
+                                              uint32_t& n_blocks, uint32_t& n_draws) {
+  constexpr int DEG = 2 * NDIM;
+  uint32_t u0, u1, u2;
+  bond_count<DEG>(x, u0, u1, u2);
+  uint32_t acc, k1, k2, k3 = 0u;
+  if (NDIM == 2) {
+    acc = u1 | u2;        // u >= 2
+    k1 = u0 & ~acc;       // u == 1
+    k2 = ~(u0 | acc);     // u == 0
+  } else {
+    acc = u2 | (u1 & u0);           // u >= 3
+    k1 = u1 & ~u0 & ~u2;            // u == 2
+    k2 = u0 & ~u1 & ~u2;            // u == 1
+    k3 = ~(u0 | u1 | u2);           // u == 0
+  }
+  if (LEV == 0) return acc;
+  uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
+  draw_compare<LEV>(seed, ci, t, quad0, T1, T2, T3, c1, c2, c3);
+  if (STATS) {
+    const uint32_t need = k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u);
+    n_blocks += 8u;
+    n_draws += __popc(need & valid_lanes);
+  }
+  return acc | (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u);
+}
+
+// One colour half-sweep of this thread's site words.  EVEN2D: a 2-D torus
+// walked with an even number of lines per pass, so every line of the thread
+// has the same x parity o and the x-shift neighbour sits at a fixed offset;
+// otherwise the general walk (3-D, or an odd pass).  The word is written back
+// unconditionally: no other thread reads it during this half-sweep.
+template <int NDIM, int LEV, bool FLIPS, bool STATS, bool EVEN2D>
+__device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, const BpWalk& w, uint32_t p,
+                                              uint64_t seed, uint32_t t, uint32_t quad0, uint32_t T1, uint32_t T2,
+                                              uint32_t T3, uint32_t valid_lanes, uint32_t* fplanes,
+                                              uint32_t& n_blocks, uint32_t& n_draws) {
+  constexpr int DEG = 2 * NDIM;
+  const uint32_t other = (1u - 2u * p) * w.half;
+  uint32_t own = p * w.half + w.line0 * w.hx + w.m;
+  if (EVEN2D) {
+    // lines y0, y0 + lp, ... < Ly; only the first (y = 0) and the last
+    // (y = Ly - 1) can wrap in y, so those two run with per-lane offsets and
+    // the lines between with fixed ones
+    const uint32_t o = (p + w.y0) & 1u;
+    // x-shift neighbour (+x when o = 1, -x when o = 0) and the weight-sign
+    // bits of the shifted and the same-column bonds
+    const uint32_t dx = o ? w.d_up : w.d_dn;
+    const int bit_shift = o ? 0 : 1, bit_same = 1 - bit_shift;
+    uint32_t ci = w.line0 * w.Lx + 2u * w.m + o;
+    uint32_t* p_own = lds + own;
+    const uint8_t* p_wl = wl + own;
+    const uint32_t* p_nb = lds + own + other;  // same-column neighbour word
+    const uint32_t n_lines = (w.Ly - 1u - w.y0) / w.lp + 1u;  // this thread's lines (y0 < Ly)
+    const uint32_t step = w.own_step;
+    auto visit = [&](uint32_t dyp, uint32_t dym) {
+      const uint32_t s = *p_own;
+      const uint32_t wp = *p_wl;
+      uint32_t x[4];
+      x[0] = xor3(s, p_nb[dx], (uint32_t)__builtin_amdgcn_sbfe((int)wp, bit_shift, 1));
+      x[1] = xor3(s, p_nb[0], (uint32_t)__builtin_amdgcn_sbfe((int)wp, bit_same, 1));
+      x[2] = xor3(s, p_nb[dyp], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 2, 1));
+      x[3] = xor3(s, p_nb[dym], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 3, 1));
+      const uint32_t F = bp_decide<NDIM, LEV, STATS>(x, seed, ci, t, quad0, T1, T2, T3, valid_lanes, n_blocks, n_draws);
+      *p_own = s ^ F;
+      if (FLIPS) add_planes<8>(fplanes, F);
+      p_own += step;
+      p_wl += step;
+      p_nb += step;
+      ci += w.ci_step;
+    };
+    // first line
+    visit(w.y0 + 1u == w.Ly ? w.dyp_wrap : w.row, w.y0 == 0u ? w.dym_wrap : 0u - w.row);
+    if (n_lines >= 2u) {
+      for (uint32_t k = 2u; k < n_lines; ++k) visit(w.row, 0u - w.row);
+      const uint32_t y_last = w.y0 + (n_lines - 1u) * w.lp;
+      visit(y_last + 1u == w.Ly ? w.dyp_wrap : w.row, 0u - w.row);
+    }
+    return;
+  }
+  uint32_t ci0 = w.line0 * w.Lx + 2u * w.m;
+  uint32_t y = w.y0, z = w.z0;
+  for (uint32_t line = w.line0; line < w.lines; line += w.lp) {
+    const uint32_t o = (p + y + z) & 1u;
+    const uint32_t base = own + other;
+    uint32_t nb[DEG];
+    nb[0] = base + (o ? w.d_up : 0u);
+    nb[1] = base + (o ? 0u : w.d_dn);
+    nb[2] = base + (y + 1u == w.Ly ? w.dyp_wrap : w.row);
+    nb[3] = base + (y == 0u ? w.dym_wrap : 0u - w.row);
+    if (NDIM == 3) {
+      nb[DEG - 2] = base + (z + 1u == w.Lz ? w.dzp_wrap : w.plane);
+      nb[DEG - 1] = base + (z == 0u ? w.dzm_wrap : 0u - w.plane);
+    }
+    const uint32_t s = lds[own];
+    const uint32_t wp = wl[own];
+    uint32_t x[DEG];
+#pragma unroll
+    for (int d = 0; d < DEG; ++d) {
+      // unsatisfied bond: w s_i s_j = +1  <=>  (s_i == s_j) == (w == +1)
+      const uint32_t plus = (uint32_t)__builtin_amdgcn_sbfe((int)wp, d, 1);  // all ones iff w = +1
+      x[d] = xor3(s, lds[nb[d]], plus);
+    }
+    const uint32_t F = bp_decide<NDIM, LEV, STATS>(x, seed, ci0 + o, t, quad0, T1, T2, T3, valid_lanes, n_blocks,
+                                                   n_draws);
+    lds[own] = s ^ F;
+    if (FLIPS) add_planes<8>(fplanes, F);
+    own += w.own_step;
+    ci0 += w.ci_step;
+    y += w.lp_y;
+    z += w.lp_z;
+    if (y >= w.Ly) {
+      y -= w.Ly;
+      z += 1u;
+    }
+  }
+}
+
+template <int NDIM, bool FLIPS, bool STATS, bool EVEN2D>
+__device__ __forceinline__ void bp_half_sweep_lev(int lev, uint32_t* lds, const uint8_t* wl, const BpWalk& w, uint32_t p,
+                                                  uint64_t seed, uint32_t t, uint32_t quad0, uint32_t T1, uint32_t T2,
+                                                  uint32_t T3, uint32_t valid_lanes, uint32_t* fplanes,
+                                                  uint32_t& n_blocks, uint32_t& n_draws) {
+  if (lev == 0)
+    bp_half_sweep<NDIM, 0, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
+                                                 n_blocks, n_draws);
+  else if (lev == 1)
+    bp_half_sweep<NDIM, 1, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
+                                                 n_blocks, n_draws);
+  else if (NDIM == 2 || lev == 2)
+    bp_half_sweep<NDIM, 2, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
+                                                 n_blocks, n_draws);
+  else
+    bp_half_sweep<NDIM, 3, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
+                                                 n_blocks, n_draws);
+}
+
 template <int NDIM, bool FLIPS, bool STATS>
 __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
   extern __shared__ uint32_t lds[];
@@ -160,25 +313,36 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
     wl[slot] = (uint8_t)(~a.wbits[slot] & ((1u << DEG) - 1u));
   }
 
-  // ---- this thread's sites (as in the four-replica kernel) ------------------
+  // ---- this thread's sites ---------------------------------------------------
+  BpWalk w;
   const uint32_t hx = (uint32_t)L.hx;
-  const uint32_t m = (uint32_t)tid % hx;
-  const uint32_t line0 = (uint32_t)tid / hx;
-  const uint32_t m_up = (m + 1u == hx) ? 0u : m + 1u;
-  const uint32_t m_dn = (m == 0u) ? hx - 1u : m - 1u;
-  const uint32_t lp = (uint32_t)a.lp;
-  const uint32_t Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz;
-  const uint32_t lp_z = NDIM == 2 ? 0u : lp / Ly;
-  const uint32_t lp_y = lp - lp_z * Ly;
-  const uint32_t z0 = NDIM == 2 ? 0u : line0 / Ly;
-  const uint32_t y0 = line0 - z0 * Ly;
-  const bool active = tid < (int)(hx * lp);
-  const uint32_t d_up = m_up - m, d_dn = m_dn - m;
-  const uint32_t row = hx, plane = hx * Ly;
-  const uint32_t dyp_wrap = row - plane, dym_wrap = plane - row;
-  const uint32_t dzp_wrap = plane - plane * Lz, dzm_wrap = plane * Lz - plane;
-  const uint32_t own_step = lp * hx;
-  const uint32_t ci_step = lp * (uint32_t)L.Lx;
+  w.hx = hx;
+  w.Lx = (uint32_t)L.Lx;
+  w.half = (uint32_t)L.half;
+  w.lines = (uint32_t)L.lines;
+  w.m = (uint32_t)tid % hx;
+  w.line0 = (uint32_t)tid / hx;
+  const uint32_t m_up = (w.m + 1u == hx) ? 0u : w.m + 1u;
+  const uint32_t m_dn = (w.m == 0u) ? hx - 1u : w.m - 1u;
+  w.lp = (uint32_t)a.lp;
+  w.Ly = (uint32_t)L.Ly;
+  w.Lz = (uint32_t)L.Lz;
+  w.lp_z = NDIM == 2 ? 0u : w.lp / w.Ly;
+  w.lp_y = w.lp - w.lp_z * w.Ly;
+  w.z0 = NDIM == 2 ? 0u : w.line0 / w.Ly;
+  w.y0 = w.line0 - w.z0 * w.Ly;
+  const bool active = tid < (int)(hx * w.lp);
+  w.d_up = m_up - w.m;
+  w.d_dn = m_dn - w.m;
+  w.row = hx;
+  w.plane = hx * w.Ly;
+  w.dyp_wrap = w.row - w.plane;
+  w.dym_wrap = w.plane - w.row;
+  w.dzp_wrap = w.plane - w.plane * w.Lz;
+  w.dzm_wrap = w.plane * w.Lz - w.plane;
+  w.own_step = w.lp * hx;
+  w.ci_step = w.lp * w.Lx;
+  const bool even2d = NDIM == 2 && (w.lp & 1u) == 0u;
   __syncthreads();
   if (bad) atomicOr(&extra[64], bad);
 
@@ -191,75 +355,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
   for (int t = a.t_begin; t < a.t_end; ++t) {
     const uint32_t* tr = a.thr + (size_t)t * NDIM;
     const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
-    for (int p = 0; p < 2; ++p) {
+    const int lev = T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
+    for (uint32_t p = 0; p < 2u; ++p) {
       if (active) {
-        const uint32_t other = (uint32_t)(1 - 2 * p) * (uint32_t)L.half;
-        uint32_t own = (uint32_t)p * (uint32_t)L.half + line0 * hx + m;
-        uint32_t ci0 = line0 * (uint32_t)L.Lx + 2u * m;
-        uint32_t y = y0, z = z0;
-        for (uint32_t line = line0; line < (uint32_t)L.lines; line += lp) {
-          const uint32_t o = (p + y + z) & 1u;
-          const uint32_t base = own + other;
-          uint32_t nb[DEG];
-          nb[0] = base + (o ? d_up : 0u);
-          nb[1] = base + (o ? 0u : d_dn);
-          nb[2] = base + (y + 1u == Ly ? dyp_wrap : row);
-          nb[3] = base + (y == 0u ? dym_wrap : 0u - row);
-          if (NDIM == 3) {
-            nb[DEG - 2] = base + (z + 1u == Lz ? dzp_wrap : plane);
-            nb[DEG - 1] = base + (z == 0u ? dzm_wrap : 0u - plane);
-          }
-          const uint32_t ci = ci0 + o;
-          const uint32_t s = lds[own];
-          const uint32_t wp = wl[own];
-          uint32_t x[DEG];
-#pragma unroll
-          for (int d = 0; d < DEG; ++d) {
-            // unsatisfied bond: w s_i s_j = +1  <=>  (s_i == s_j) == (w == +1)
-            const uint32_t plus = (uint32_t)__builtin_amdgcn_sbfe((int)wp, d, 1);  // all ones iff w = +1
-            x[d] = xor3(s, lds[nb[d]], plus);
-          }
-          uint32_t u0, u1, u2;
-          bond_count<DEG>(x, u0, u1, u2);
-          // dE = 2 deg - 4u: flip when u >= deg/2; else k = deg/2 - u
-          uint32_t acc, k1, k2, k3 = 0u;
-          if (NDIM == 2) {
-            acc = u1 | u2;        // u >= 2
-            k1 = u0 & ~acc;       // u == 1
-            k2 = ~(u0 | acc);     // u == 0
-          } else {
-            acc = u2 | (u1 & u0);           // u >= 3
-            k1 = u1 & ~u0 & ~u2;            // u == 2
-            k2 = u0 & ~u1 & ~u2;            // u == 1
-            k3 = ~(u0 | u1 | u2);           // u == 0
-          }
-          uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-          if (T1 != 0u) {
-            // thresholds decrease with k, so the nonzero ones are a prefix
-            if (T2 == 0u)
-              draw_compare<1>(a.seed, ci, (uint32_t)t, quad0, T1, T2, T3, c1, c2, c3);
-            else if (NDIM == 2 || T3 == 0u)
-              draw_compare<2>(a.seed, ci, (uint32_t)t, quad0, T1, T2, T3, c1, c2, c3);
-            else
-              draw_compare<3>(a.seed, ci, (uint32_t)t, quad0, T1, T2, T3, c1, c2, c3);
-            if (STATS) {
-              const uint32_t need = k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u);
-              n_blocks += 8u;
-              n_draws += __popc(need & valid_lanes);
-            }
-          }
-          const uint32_t F = acc | (k1 & c1) | (k2 & c2) | (k3 & c3);
-          if (F) lds[own] = s ^ F;
-          if (FLIPS) add_planes<8>(fplanes, F);
-          own += own_step;
-          ci0 += ci_step;
-          y += lp_y;
-          z += lp_z;
-          if (y >= Ly) {
-            y -= Ly;
-            z += 1u;
-          }
-        }
+        if (even2d)
+          bp_half_sweep_lev<NDIM, FLIPS, STATS, true>(lev, lds, wl, w, p, a.seed, (uint32_t)t, quad0, T1, T2, T3,
+                                                      valid_lanes, fplanes, n_blocks, n_draws);
+        else
+          bp_half_sweep_lev<NDIM, FLIPS, STATS, false>(lev, lds, wl, w, p, a.seed, (uint32_t)t, quad0, T1, T2, T3,
+                                                       valid_lanes, fplanes, n_blocks, n_draws);
       }
       __syncthreads();
     }
@@ -273,28 +377,29 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) eplanes[k] = 0u;
     if (active) {
-      for (int p = 0; p < 2; ++p) {
-        const uint32_t other = (uint32_t)(1 - 2 * p) * (uint32_t)L.half;
-        uint32_t own = (uint32_t)p * (uint32_t)L.half + line0 * hx + m;
-        uint32_t y = y0, z = z0;
-        for (uint32_t line = line0; line < (uint32_t)L.lines; line += lp) {
+      for (uint32_t p = 0; p < 2u; ++p) {
+        const uint32_t other = (1u - 2u * p) * w.half;
+        uint32_t own = p * w.half + w.line0 * hx + w.m;
+        uint32_t y = w.y0, z = w.z0;
+        for (uint32_t line = w.line0; line < w.lines; line += w.lp) {
           const uint32_t o = (p + y + z) & 1u;
           const uint32_t base = own + other;
           const uint32_t s = lds[own];
           const uint32_t wp = wl[own];
-          uint32_t e = xor3(s, lds[base + (o ? d_up : 0u)], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 0, 1));
+          uint32_t e = xor3(s, lds[base + (o ? w.d_up : 0u)], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 0, 1));
           add_planes<12>(eplanes, e);
-          e = xor3(s, lds[base + (y + 1u == Ly ? dyp_wrap : row)], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 2, 1));
+          e = xor3(s, lds[base + (y + 1u == w.Ly ? w.dyp_wrap : w.row)], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 2, 1));
           add_planes<12>(eplanes, e);
           if (NDIM == 3) {
-            e = xor3(s, lds[base + (z + 1u == Lz ? dzp_wrap : plane)], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 4, 1));
+            e = xor3(s, lds[base + (z + 1u == w.Lz ? w.dzp_wrap : w.plane)],
+                     (uint32_t)__builtin_amdgcn_sbfe((int)wp, 4, 1));
             add_planes<12>(eplanes, e);
           }
-          own += own_step;
-          y += lp_y;
-          z += lp_z;
-          if (y >= Ly) {
-            y -= Ly;
+          own += w.own_step;
+          y += w.lp_y;
+          z += w.lp_z;
+          if (y >= w.Ly) {
+            y -= w.Ly;
             z += 1u;
           }
         }

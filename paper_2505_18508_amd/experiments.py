@@ -53,7 +53,8 @@ def first_hit_seconds(window_best, target, S, seconds):
 
 def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000, run_seeds=(201, 202, 203, 204, 205),
                    train_seeds=tuple(range(1001, 1014)), n_traj=100000, epochs=20, batch=8192, long_sweeps=200000,
-                   label="relative", train_dims=None, train_replicas=None, log=print):
+                   label="relative", train_dims=None, train_replicas=None, known_best=None, save_model=None,
+                   log=print):
     import torch
 
     t_start = time.time()
@@ -61,7 +62,7 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
     RT = R if train_replicas is None else train_replicas
     instances = [(train_dims, ws, 5000 + ws) for ws in train_seeds]
     per_instance = len(learn.checkpoints(S, window))
-    X, Y = learn.trajectories(instances, RT, S, window, label=label)
+    X, Y = learn.trajectories(instances, RT, S, window, label=label, log=log)
     # keep the first n_traj trajectories (instance-major, then replica)
     rows = []
     for k in range(len(instances)):
@@ -76,6 +77,8 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
     log("training rows %d (%d trajectories x %d checkpoints), %.1f s" % (X.shape[0], X.shape[0] // per_instance,
                                                                            per_instance, time.time() - t_start))
     model, history = learn.train(X, Y, epochs=epochs, batch=batch, log=log, label=label)
+    if save_model:
+        model.save(save_model)
 
     g = create_graph(list(dims), weight_seed)
     for method in learn.METHODS:  # untimed warm-up of every code path
@@ -93,10 +96,15 @@ def ttt_experiment(dims=(100, 200), weight_seed=81, R=8192, S=40000, window=2000
     log("  long plain run (%d sweeps): best %d, %.1f s" % (long_sweeps, long_best, long["seconds"]))
     compared_best = max(all_best)
     summary = {"n_edges": g.n_edges, "long_run_best": long_best, "compared_runs_best": compared_best, "targets": {}}
-    # two readings of "the best cut found for the instance": the best of the
-    # compared runs (every method sees the same target), and that together
-    # with one much longer plain run
-    for tname, best in (("compared_runs", compared_best), ("with_long_run", max(compared_best, long_best))):
+    # readings of "the best cut found for the instance": the best of the
+    # compared runs (every method sees the same target), that together with
+    # one much longer plain run, and that together with the best any earlier
+    # campaign found on the instance (known_best)
+    readings = [("compared_runs", compared_best), ("with_long_run", max(compared_best, long_best))]
+    if known_best is not None:
+        readings.append(("instance_best", max(compared_best, long_best, int(known_best))))
+    summary["known_best"] = known_best
+    for tname, best in readings:
         target = metrics.target_cut(best)
         block = {"best_cut": best, "target": target, "methods": {}}
         for method in learn.METHODS:
@@ -144,6 +152,9 @@ def main(argv=None):
     ap.add_argument("--weight-seed", type=int, default=81)
     ap.add_argument("--train-dims", default=None)
     ap.add_argument("--train-replicas", type=int, default=None)
+    ap.add_argument("--known-best", type=int, default=None,
+                    help="best cut found on the instance by earlier runs (joins the instance-best target)")
+    ap.add_argument("--save-model", default=None, help="write the trained network (npz) here")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -154,7 +165,8 @@ def main(argv=None):
     s = ttt_experiment(dims=dims, weight_seed=args.weight_seed, label=args.label, train_dims=tdims,
                        train_replicas=args.train_replicas, R=args.replicas, S=args.sweeps, window=args.window, epochs=args.epochs,
                        train_seeds=tuple(range(1001, 1001 + args.train_instances)), n_traj=args.n_traj,
-                       run_seeds=tuple(range(201, 201 + args.seeds)), long_sweeps=args.long_sweeps, log=log)
+                       run_seeds=tuple(range(201, 201 + args.seeds)), long_sweeps=args.long_sweeps,
+                       known_best=args.known_best, save_model=args.save_model, log=log)
     text = json.dumps(s)
     if args.out:
         with open(args.out, "w") as fh:

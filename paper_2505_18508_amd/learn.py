@@ -125,7 +125,7 @@ def anneal(graph, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05, 
 
 
 def trajectories(instances, n_replicas, n_sweeps, window, schedule="geometric", beta0=0.05, beta1=4.0,
-                 layout="auto", label="final"):
+                 layout="auto", label="final", log=None):
     """Training rows from plain runs: features at every checkpoint, labelled
     with the end-of-trial cut / |E| (label "final"), with the cut still to
     come, (final cut - cut at the checkpoint) / |E| (label "gain"), or with
@@ -144,6 +144,8 @@ def trajectories(instances, n_replicas, n_sweeps, window, schedule="geometric", 
                      on_checkpoint=lambda k, e, f: rows.append(f.clone()),
                      on_window=lambda k, e, c: cuts.__setitem__(k, c.clone()))
         final = out["cut"]
+        if log:
+            log("  training run: %s weight seed %d, %.1f s" % ("x".join(map(str, dims)), wseed, out["seconds"]))
         if label == "relative":
             X = torch.cat(rows)
             standardize_groups(X, len(rows), R, 16)

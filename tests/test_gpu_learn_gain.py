@@ -1,9 +1,17 @@
-"""What the trained network gains over the method without it, at small
-scale: the learned-culling protocol (network trained with the library's
-kernels on plain runs of four instances, then used to cull replicas on a
-held-out fifth) against the plain all-trials run on the same instance, seeds
-and schedule.  Everything is seeded and every kernel is deterministic, so
-the comparison is exact; the energy-ranked cull is reported beside it."""
+"""What the trained network gains over the method without it.
+
+The learned-culling protocol (the network trained with the library's
+kernels on plain runs of other instances, then used to rank the replicas of
+a held-out instance) is compared on the same instance, seeds and schedule
+with the plain all-trials run and with the same cull ranked by the current
+energy alone, which isolates the network's contribution.  Everything is
+seeded and every kernel is deterministic, so each comparison is exact.
+
+Clones are correlated, so eq. (3)'s success probability flatters any culled
+form; the network is therefore judged against the energy ranking by the
+mean end-of-trial cut of each batch, which copying replicas cannot inflate
+(a copy ends where its own trajectory takes it).  The trained network's gain
+has no pin other than this comparison."""
 import math
 
 import pytest
@@ -11,8 +19,40 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("label", ["final", "relative"])
-def test_learned_culling_reaches_target_faster_than_plain(label):
+def _means(s, method):
+    return [r["mean"] for r in s["runs"][method]]
+
+
+def test_learned_culling_beats_plain_and_energy_ranking_on_the_20000_spin_torus():
+    """100 x 200 torus (weight seed 81), 1,024 replicas, 40,000 sweeps, a
+    ranking every 2,000 sweeps; network trained on 13 other instances of the
+    same shape; run seeds 201-207."""
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2505_18508_amd import experiments
+
+    s = experiments.ttt_experiment(dims=(100, 200), weight_seed=81, R=1024, S=40000, window=2000,
+                                   run_seeds=tuple(range(201, 208)), train_seeds=tuple(range(1001, 1014)),
+                                   n_traj=13312, epochs=20, batch=8192, long_sweeps=40000, label="relative", log=print)
+    L, E, P = _means(s, "learned"), _means(s, "energy"), _means(s, "plain")
+    print("mean final cut per seed: learned", L, "energy", E, "plain", P)
+    blk = s["targets"]["compared_runs"]
+    ttt = {m: blk["methods"][m]["median_TTT_s"] for m in blk["methods"]}
+    print("target", blk["target"], "median TTT (s)", ttt)
+    assert s["train_loss"][-1] < s["train_loss"][0]
+    # over the method without culling: every seed ends higher, and the target is reached sooner
+    assert all(l > p for l, p in zip(L, P))
+    assert math.isfinite(ttt["learned"]) and ttt["learned"] < ttt["plain"]
+    # over culling without the network: a higher mean end-of-trial cut on most seeds and on average
+    assert sum(l > e for l, e in zip(L, E)) >= 5
+    assert sum(L) > sum(E)
+
+
+def test_learned_culling_with_raw_features_beats_plain_at_small_scale():
+    """50 x 100 torus, 1,024 replicas, 4,000 sweeps, network on raw features
+    (label "final"): faster to the target than the plain run.  (At this size
+    the energy ranking alone does as well as the network.)"""
     import torch
 
     assert torch.cuda.is_available()
@@ -20,11 +60,10 @@ def test_learned_culling_reaches_target_faster_than_plain(label):
 
     s = experiments.ttt_experiment(dims=(50, 100), weight_seed=3001, R=1024, S=4000, window=400,
                                    run_seeds=(201, 202, 203), train_seeds=(1001, 1002, 1003, 1004), n_traj=4096,
-                                   epochs=20, batch=8192, long_sweeps=4000, label=label, log=print)
+                                   epochs=20, batch=8192, long_sweeps=4000, label="final", log=print)
     blk = s["targets"]["compared_runs"]
     ttt = {m: blk["methods"][m]["median_TTT_s"] for m in blk["methods"]}
-    print("target", blk["target"], "median TTT (s)", ttt)
+    print("target", blk["target"], "median TTT (s)", ttt, "energy ranking", ttt["energy"])
     assert s["train_loss"][-1] < s["train_loss"][0]
-    assert math.isfinite(ttt["learned"])
-    assert ttt["learned"] < ttt["plain"]
-    assert blk["learned_over_plain_TTT"] < 1.0
+    assert math.isfinite(ttt["learned"]) and ttt["learned"] < ttt["plain"]
+    assert all(l > p for l, p in zip(_means(s, "learned"), _means(s, "plain")))

@@ -68,6 +68,23 @@ def run_oracle(dims, weight_seed, seed, R, S, begin=0, end=None, schedule="linea
     return s, cut, en, fl
 
 
+def run_oracle_blocks(dims, weight_seed, seed, starts, width, S, begin=0, end=None, schedule="linear", beta0=0.1,
+                      beta1=3.0, spins0=None):
+    """Oracle outputs of the replica blocks [start, start + width), computed
+    side by side on host threads (the C oracle keeps no global state and
+    ctypes releases the interpreter lock during the call): {start: outputs}."""
+    import concurrent.futures
+    import os
+
+    def one(start):
+        sp = None if spins0 is None else spins0[start:start + width]
+        return start, run_oracle(dims, weight_seed, seed, width, S, begin, end, schedule, beta0, beta1, spins0=sp,
+                                 replica_begin=start)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return dict(ex.map(one, list(starts)))
+
+
 def assert_same(gpu, orc, rows=None):
     gs, gc, ge, gf = gpu
     if rows is not None:
@@ -109,30 +126,37 @@ def test_torus50x100_full_run_bit_exact(dev, layout):
     assert_same(gpu, orc)
 
 
+_C2_ORACLE = {}
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_torus100x100_first_200_sweeps_sampled_replicas(dev, layout):
-    """All 1,024 replicas on the GPU for sweeps [0, 200) of the 10,000-sweep
-    schedule; the oracle recomputes 24 of them (first, middle, last quads)."""
+def test_torus100x100_first_200_sweeps_every_replica(dev, layout):
+    """All 1,024 replicas for sweeps [0, 200) of the 10,000-sweep schedule,
+    every one recomputed by the oracle (once, shared by the layouts)."""
     c = inputs.TORUS_100x100_R1024
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, 200, c["schedule"], c["beta0"], c["beta1"],
                   layout=layout)
-    for start in (0, 4, 508, 512, 1016, 1020):
-        orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, 200, c["schedule"], c["beta0"],
-                         c["beta1"], replica_begin=start)
-        assert_same(gpu, orc, rows=slice(start, start + 4))
+    if not _C2_ORACLE:
+        print("oracle: 1,024 replicas x 200 sweeps", flush=True)
+        _C2_ORACLE.update(run_oracle_blocks(c["dims"], c["weight_seed"], c["seed"], range(0, c["R"], 16), 16, c["S"],
+                                            0, 200, c["schedule"], c["beta0"], c["beta1"]))
+    for start, orc in sorted(_C2_ORACLE.items()):
+        assert_same(gpu, orc, rows=slice(start, start + 16))
 
 
 def test_torus100x100_full_schedule_in_bench_launch_sampled(dev):
-    """The timed configuration itself: all 1,024 replicas through the whole
-    10,000-sweep schedule in one launch of the automatically chosen packing;
-    the oracle recomputes the first and the last replica quad end to end."""
+    """The configuration of the 10,000-spin benchmark: all 1,024 replicas
+    through the whole 10,000-sweep schedule in one launch of the
+    automatically chosen packing; the oracle recomputes 16 replica quads
+    spread over the run end to end (64 replicas)."""
     c = inputs.TORUS_100x100_R1024
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, c["S"], c["schedule"], c["beta0"],
                   c["beta1"], layout="auto")
-    for start in (0, c["R"] - 4):
-        print("oracle quad", start, flush=True)
-        orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, c["S"], c["schedule"], c["beta0"],
-                         c["beta1"], replica_begin=start)
+    starts = [4 * (k * (c["R"] // 4 - 1) // 15) for k in range(16)]
+    assert starts[0] == 0 and starts[-1] == c["R"] - 4
+    print("oracle quads", starts, flush=True)
+    for start, orc in run_oracle_blocks(c["dims"], c["weight_seed"], c["seed"], starts, 4, c["S"], 0, c["S"],
+                                        c["schedule"], c["beta0"], c["beta1"]).items():
         assert_same(gpu, orc, rows=slice(start, start + 4))
 
 
@@ -153,15 +177,19 @@ def test_torus100x200_full_schedule_in_bench_launch_sampled(dev):
     """The 20,000-spin workload as timed: all 8,192 replicas through the whole
     40,000-sweep schedule in one launch of the automatically chosen packing
     (32 replicas per word, flip counters flushed every few sweeps); the oracle
-    recomputes the last replica quad end to end."""
+    recomputes four replica quads end to end: the first, two in the middle
+    (in the first and the last of the 256 32-replica groups' halves) and the
+    last."""
     c = inputs.TORUS_100x200_R8192
     gpu = run_gpu(c["dims"], c["weight_seed"], c["seed"], c["R"], c["S"], 0, c["S"], c["schedule"], c["beta0"],
                   c["beta1"], layout="auto")
-    start = c["R"] - 4
-    print("oracle quad", start, flush=True)
-    orc = run_oracle(c["dims"], c["weight_seed"], c["seed"], 4, c["S"], 0, c["S"], c["schedule"], c["beta0"],
-                     c["beta1"], replica_begin=start)
-    assert_same(gpu, orc, rows=slice(start, start + 4))
+    starts = [0, 2732, 4100, c["R"] - 4]
+    print("oracle quads", starts, flush=True)
+    # one replica per task: a replica's whole schedule is 8e8 attempts
+    reps = run_oracle_blocks(c["dims"], c["weight_seed"], c["seed"], [q + b for q in starts for b in range(4)], 1,
+                             c["S"], 0, c["S"], c["schedule"], c["beta0"], c["beta1"])
+    for r, orc in reps.items():
+        assert_same(gpu, orc, rows=slice(r, r + 1))
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -179,7 +207,8 @@ def test_torus100x200_short_window_sampled(dev, layout):
 @pytest.mark.parametrize("dims,R", [([2, 2], 5), ([2, 4], 3), ([4, 2], 8), ([4, 6], 13), ([6, 8], 1), ([2, 6], 7),
                                     ([2, 2, 2], 6), ([4, 4, 6], 9), ([6, 8, 10], 4), ([2, 4, 2], 2),
                                     ([34, 18], 11), ([10, 1000], 3), ([6, 4], 37), ([8, 6, 4], 33),
-                                    ([8, 6], 6), ([12, 10], 17), ([4, 1000], 5), ([2, 8, 6], 3), ([20, 34], 9)])
+                                    ([8, 6], 6), ([12, 10], 17), ([4, 1000], 5), ([2, 8, 6], 3), ([20, 34], 9),
+                                    ([14, 600], 6)])
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_small_and_ragged_tori(dev, dims, R, layout):
     if layout == "bs4" and not bs4_ok(dims):
@@ -465,6 +494,24 @@ def test_streamed_stress_tori_sampled(dev, dims):
     for start in (0, 60):
         orc = run_oracle(dims, wseed, 77, 4, 2000, 0, 6, "geometric", 0.05, 4.0, replica_begin=start)
         assert_same(gpu, orc, rows=slice(start, start + 4))
+
+
+@pytest.mark.parametrize("dims", [[1000, 1000], [64, 64, 64]])
+def test_streamed_stress_tori_cold_end_every_replica(dev, dims):
+    """The full streamed launch shape (256 replicas) at the cold end of the
+    2,000-sweep schedule: sweeps [1990, 2000) from a seeded state, where the
+    second threshold level has vanished and almost every draw is rejected;
+    all 256 replicas recomputed by the oracle from the same state."""
+    wseed = 1000 if len(dims) == 2 else 643
+    R = 256
+    n = int(np.prod(dims))
+    start = inputs.random_spins(4242, R, n)
+    gpu = run_gpu(dims, wseed, 7, R, 2000, 1990, 2000, schedule="geometric", beta0=0.05, beta1=4.0, spins0=start,
+                  layout="auto")
+    print("oracle: 256 replicas x 10 sweeps", flush=True)
+    for b, orc in run_oracle_blocks(dims, wseed, 7, range(0, R, 16), 16, 2000, 1990, 2000, "geometric", 0.05, 4.0,
+                                    spins0=start).items():
+        assert_same(gpu, orc, rows=slice(b, b + 16))
 
 
 def test_streamed_matches_on_chip_layouts(dev):
