@@ -45,7 +45,7 @@ def one_campaign(g, n_replicas, n_sweeps, seed, schedule="geometric", beta0=0.05
 
 
 def campaign(dims=(100, 200), weight_seed=81, n_replicas=1024, sweeps=DEFAULT_SWEEPS, seed=301,
-             schedule="geometric", beta0=0.05, beta1=4.0, quality=0.999, log=None):
+             schedule="geometric", beta0=0.05, beta1=4.0, quality=0.999, reference_best=None, log=None):
     g = create_graph(list(dims), weight_seed)
     rows = []
     for S in sweeps:
@@ -53,7 +53,9 @@ def campaign(dims=(100, 200), weight_seed=81, n_replicas=1024, sweeps=DEFAULT_SW
         rows.append((S, cuts, secs))
         if log:
             log("S %8d: best %d  mean %.2f  %.3f s" % (S, cuts.max(), cuts.mean(), secs))
-    best = max(int(c.max()) for _, c, _ in rows)
+    # the best cut found for the instance: these campaigns', or a larger one
+    # found earlier (reference_best)
+    best = max([int(c.max()) for _, c, _ in rows] + ([int(reference_best)] if reference_best else []))
     target = metrics.target_cut(best, quality)
     out = {"dims": list(dims), "weight_seed": weight_seed, "n_edges": g.n_edges, "replicas": n_replicas,
            "schedule": [schedule, beta0, beta1], "best_cut": best, "quality": quality, "target": target,
@@ -87,13 +89,15 @@ def main(argv=None):
     ap.add_argument("--sweeps", default=",".join(str(s) for s in DEFAULT_SWEEPS))
     ap.add_argument("--seed", type=int, default=301)
     ap.add_argument("--quality", type=float, default=0.999)
+    ap.add_argument("--reference-best", type=int, default=0,
+                    help="best cut found on the instance by earlier runs (joins the target's best)")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     dims = tuple(int(v) for v in args.dims.split("x"))
     sweeps = tuple(int(v) for v in args.sweeps.split(","))
     t0 = time.time()
     out = campaign(dims, args.weight_seed, args.replicas, sweeps, args.seed, quality=args.quality,
-                   log=lambda m: print(m, flush=True))
+                   reference_best=args.reference_best or None, log=lambda m: print(m, flush=True))
     out["wall_seconds"] = time.time() - t0
     text = json.dumps(out)
     if args.out:

@@ -98,3 +98,21 @@ def test_cpu_baseline_windows_large_lattices_and_samples_the_batch():
     b = bench.cpu_workload("batch4tori")
     assert b["dims"] == [100, 200] and b["S"] == 20000 and b["R"] == 4096 and "100x200 instance" in b["sample_of"]
     assert bench.cpu_workload("torus100x100") is bench.WORKLOADS["torus100x100"]
+
+
+def test_ttt_leg_configuration_and_model():
+    """The time-to-target leg's network loads without unpickling, is a
+    16-64-64-1 network of the relative label, and its schedule gives 19
+    rankings per trial."""
+    import numpy as np
+
+    from paper_2505_18508_amd import learn
+
+    W = bench.TTT
+    with np.load(os.path.join(ROOT, W["model"]), allow_pickle=False) as z:
+        assert z["params"].shape == (5313,) and z["mean"].shape == (16,) and z["std"].shape == (16,)
+        assert learn.LABELS[int(z["label"])] == "relative"
+        assert np.isfinite(z["params"]).all()
+    assert len(learn.checkpoints(W["S"], W["window"])) == 19
+    assert W["dims"] == bench.WORKLOADS[bench.DEFAULT_WORKLOAD]["dims"]
+    assert W["weight_seed"] == bench.WORKLOADS[bench.DEFAULT_WORKLOAD]["weight_seed"]
