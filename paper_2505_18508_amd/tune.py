@@ -144,6 +144,90 @@ def tuned_run_trials(graph, spins, seed, n_sweeps, sweep_begin=0, sweep_end=None
 
 
 
+def batch_candidates(dims):
+    """(layout, block_threads) pairs for one instance of a persistent batch:
+    the four-replica packings at the tile sizes candidates() gives."""
+    return [(l, bt) for l, bt in candidates(dims, 4, cus=1 << 30) if l in ("bs4", "i8")]
+
+
+def tune_batch(graphs, runs, fraction=0.02, repeats=3, log=None):
+    """Per-instance (layout, block_threads) of a persistent batch.
+
+    Coordinate descent over the instances, costliest first: each candidate
+    for one instance, the others at their current picks, times the whole
+    batch on a window of every run's schedule cut to `fraction` of its
+    length (so the instances keep their relative costs); every candidate
+    plan must return the same spins, cuts, energies and flip counts as the
+    default plan (checked).  runs are Batch run dicts (their buffers are not
+    touched).  Returns (picks, table): picks[k] = (layout, block_threads)
+    with ("auto", 0) the library's default, table = timed plans."""
+    import torch
+
+    from . import Batch
+
+    short = []
+    for run in runs:
+        b = run.get("sweep_begin", 0)
+        e = run.get("sweep_end") or run["n_sweeps"]
+        w = max(1, int(round((e - b) * fraction)))
+        R = run["spins"].shape[0]
+        dev = run["spins"].device
+        short.append(dict(run, sweep_begin=b, sweep_end=b + w, spins0=run["spins"].clone(),
+                          cut=torch.zeros(R, dtype=torch.int64, device=dev),
+                          energy=torch.zeros(R, dtype=torch.int64, device=dev),
+                          flips=torch.zeros(R, dtype=torch.int32, device=dev)))
+
+    def timed(picks):
+        rs = []
+        for (layout, bt), s in zip(picks, short):
+            r = {k: v for k, v in s.items() if k != "spins0"}
+            r.update(layout=layout, block_threads=bt, spins=s["spins0"].clone())
+            rs.append(r)
+        try:
+            batch = Batch(graphs, rs)
+        except IsingError as e:
+            if e.code == E_UNSUPPORTED:
+                return None, None
+            raise
+        ms = []
+        for rep in range(repeats + 1):
+            for r, s in zip(rs, short):
+                r["spins"].copy_(s["spins0"])
+            start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            start.record()
+            batch.run()
+            end.record()
+            end.synchronize()
+            if rep > 0:  # the first run is the warm-up
+                ms.append(start.elapsed_time(end))
+        out = [t.clone() for r in rs for t in (r["spins"], r["cut"], r["energy"], r["flips"])]
+        batch.close()
+        return sorted(ms)[len(ms) // 2], out
+
+    picks = [("auto", 0)] * len(graphs)
+    best_ms, ref = timed(picks)
+    table = [(list(picks), best_ms)]
+    if log:
+        log("default plan: %.3f ms" % best_ms)
+    order = sorted(range(len(graphs)), key=lambda k: -graphs[k].n * runs[k]["spins"].shape[0] * (
+        (runs[k].get("sweep_end") or runs[k]["n_sweeps"]) - runs[k].get("sweep_begin", 0)))
+    for k in order:
+        for cand in batch_candidates(graphs[k].dims):
+            trial = list(picks)
+            trial[k] = cand
+            ms, out = timed(trial)
+            if ms is None:
+                continue
+            if not all(bool(torch.equal(a, b)) for a, b in zip(ref, out)):
+                raise AssertionError("batch plan %s changed the results" % (trial,))
+            table.append((trial, ms))
+            if log:
+                log("instance %d %-4s block %4d: %.3f ms" % (k, cand[0], cand[1], ms))
+            if ms < best_ms:
+                best_ms, picks = ms, trial
+    return picks, table
+
+
 def main(argv=None):
     """Time every candidate launch shape of one torus and replica count and
     print them with the pick and the library's default (AUTO) choice."""

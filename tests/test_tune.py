@@ -56,3 +56,41 @@ def test_tuning_picks_identical_fastest_shape(tmp_path):
     tune.tuned_run_trials(g, b, 5, 500, schedule="geometric", beta0=0.05, beta1=4.0, path=path)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_batch_candidates_are_four_replica_tiles():
+    c = tune.batch_candidates([100, 140])
+    assert {l for l, _ in c} == {"i8", "bs4"}
+    assert all(bt % 70 == 0 and 0 < bt <= 1024 for _, bt in c)  # multiples of Lx/2 = 70
+    assert tune.batch_candidates([2, 4096]) == []
+
+
+@pytest.mark.gpu
+def test_batch_tuning_keeps_results_and_is_used_by_the_plan():
+    """The tuner's per-instance picks give the default plan's results bit for
+    bit, and a batch built with them equals single runs."""
+    import torch
+
+    import paper_2505_18508_amd as ising
+
+    specs = [([20, 30], 3, 11, 16, 400), ([24, 40], 4, 12, 32, 600), ([18, 26], 5, 13, 8, 300)]
+    graphs, runs = [], []
+    for dims, ws, seed, R, S in specs:
+        g = ising.create_graph(dims, ws)
+        graphs.append(g)
+        runs.append(dict(seed=seed, n_sweeps=S, schedule="geometric", beta0=0.05, beta1=4.0,
+                         spins=torch.zeros((R, g.n), dtype=torch.int8, device="cuda"),
+                         cut=torch.zeros(R, dtype=torch.int64, device="cuda")))
+    picks, table = tune.tune_batch(graphs, runs, fraction=0.5, repeats=1, log=print)
+    assert len(picks) == 3 and len(table) > 3
+    tuned = [dict(r, layout=l, block_threads=bt) for r, (l, bt) in zip(runs, picks)]
+    b = ising.Batch(graphs, tuned)
+    b.run()
+    torch.cuda.synchronize()
+    for g, run in zip(graphs, tuned):
+        s = torch.zeros_like(run["spins"])
+        c = torch.zeros_like(run["cut"])
+        ising.run_trials(g, s, run["seed"], run["n_sweeps"], schedule="geometric", beta0=0.05, beta1=4.0, cut=c)
+        torch.cuda.synchronize()
+        assert torch.equal(s, run["spins"]) and torch.equal(c, run["cut"])
+    b.close()
