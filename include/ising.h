@@ -396,8 +396,9 @@ int ising_adam_step(float* params, const float* grad, float* m, float* v, int64_
                     float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Column means and standard deviations (population, floored at 1e-6) of a
- * device float [rows][16] table, computed in double with a fixed summation
- * order; mean, std: device float [16].  Asynchronous. */
+ * device float [rows][16] table, computed in double in two passes (the mean,
+ * then the squared deviations from it) with a fixed summation order;
+ * mean, std: device float [16].  Asynchronous. */
 int ising_feature_stats(const float* x, int64_t rows, float* mean, float* std, void* stream);
 
 /* In place, for every group g and column c of a device float
@@ -431,6 +432,15 @@ int ising_cull_clone(const float* score, int64_t n_replicas, int64_t n_spins, in
  * ISING_E_ARG.  Asynchronous. */
 int ising_final_cut_score(const ising_graph* g, const float* gain, const float* features, int64_t n_replicas,
                           float* score, void* stream);
+
+/* Training labels from end-of-trial cuts: out[r] = (final_cut[r] - now_cut[r])
+ * * scale, computed in double and rounded to float once (now_cut NULL: 0).
+ * With scale = 1/|E| and now_cut the cut at a checkpoint this is the cut a
+ * replica still gains; without now_cut, its end-of-trial cut / |E|.
+ *   final_cut, now_cut  device int64 [R];  out device float [R].
+ * 0 <= R <= 2^31 - 1 and scale finite, else ISING_E_ARG.  Asynchronous. */
+int ising_cut_labels(const int64_t* final_cut, const int64_t* now_cut, int64_t n_replicas, double scale,
+                     float* out, void* stream);
 
 /* score[r] = -energy[r] (the energy-ranked baseline of culling);
  * 0 <= n_replicas <= 2^31 - 1, else ISING_E_ARG.  Asynchronous. */

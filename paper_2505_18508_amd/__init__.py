@@ -33,6 +33,7 @@ EXPORTED = [
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
     "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy", "ising_final_cut_score",
     "ising_pt_create", "ising_pt_run", "ising_pt_state", "ising_pt_destroy", "ising_standardize_groups",
+    "ising_cut_labels",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -106,6 +107,7 @@ def lib():
         L.ising_feature_stats.argtypes = [vp, i64, vp, vp, vp]
         L.ising_cull_clone.argtypes = [vp, i64, i64, vp, vp, vp, vp]
         L.ising_energy_score.argtypes = [vp, i64, vp, vp]
+        L.ising_cut_labels.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp]
         L.ising_schedule_beta.argtypes = [ctypes.POINTER(RunParams), i32, ctypes.POINTER(ctypes.c_double)]
         L.ising_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
         L.ising_batch_run.argtypes = [vp, vp]
@@ -461,6 +463,14 @@ def standardize_groups(x, n_groups, rows, cols, stream=None):
     table to zero mean and unit (population) deviation within the group."""
     _check(lib().ising_standardize_groups(_dev(x, "x", ("float32",), int(n_groups) * int(rows) * int(cols)),
                                           int(n_groups), int(rows), int(cols), _stream(stream)))
+
+
+def cut_labels(final_cut, out, now_cut=None, scale=1.0, stream=None):
+    """out = (final_cut - now_cut) * scale (now_cut None: 0): int64 [R] -> float32 [R]."""
+    R = final_cut.shape[0]
+    fp, np_, op = _devs((final_cut, "final_cut", ("int64",), R), (now_cut, "now_cut", ("int64",), R),
+                        (out, "out", F32, R))
+    _check(lib().ising_cut_labels(fp, np_, R, float(scale), op, _stream(stream)))
 
 
 def energy_score(energy, score, stream=None):

@@ -315,33 +315,33 @@ __global__ void k_adam(float* params, const float* grad, float* m, float* v, int
   params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Column statistics of a [rows][16] table: per-block partial sums (double),
-// then one block adds them in block order.
+// Column statistics of a [rows][16] table in two passes, as the per-group
+// standardisation does: per-block partial sums (double) of x, one block adds
+// them in block order into the mean; then per-block partial sums of
+// (x - mean)^2, added in block order into the variance.
 constexpr int kStatBlock = 256;
 constexpr int kStatGrid = 256;
 
-__global__ void __launch_bounds__(kStatBlock) k_colstats_partial(const float* x, int64_t rows, double* part) {
-  __shared__ double ssum[kStatBlock], ssq[kStatBlock];
+// PASS 0: part[b][c][0] = sum of x; PASS 1: part[b][c][1] = sum of (x - mu[c])^2.
+template <int PASS>
+__global__ void __launch_bounds__(kStatBlock) k_colstats_partial(const float* x, int64_t rows, const double* mu,
+                                                                 double* part) {
+  __shared__ double ssum[kStatBlock];
   const int col = threadIdx.x & (NF - 1), lane = threadIdx.x / NF;  // 16 row lanes per column
   const int64_t per = (rows + kStatGrid - 1) / kStatGrid;
   const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < rows ? r0 + per : rows;
-  double s = 0.0, q = 0.0;
+  const double m = PASS ? mu[col] : 0.0;
+  double s = 0.0;
   for (int64_t r = r0 + lane; r < r1; r += kStatBlock / NF) {
-    const double v = x[r * NF + col];
-    s += v;
-    q += v * v;
+    const double v = (double)x[r * NF + col] - m;
+    s += PASS ? v * v : v;
   }
   ssum[threadIdx.x] = s;
-  ssq[threadIdx.x] = q;
   __syncthreads();
   if (threadIdx.x < NF) {
-    double ts = 0.0, tq = 0.0;
-    for (int l = 0; l < kStatBlock / NF; ++l) {
-      ts += ssum[l * NF + threadIdx.x];
-      tq += ssq[l * NF + threadIdx.x];
-    }
-    part[((size_t)blockIdx.x * NF + threadIdx.x) * 2 + 0] = ts;
-    part[((size_t)blockIdx.x * NF + threadIdx.x) * 2 + 1] = tq;
+    double t = 0.0;
+    for (int l = 0; l < kStatBlock / NF; ++l) t += ssum[l * NF + threadIdx.x];
+    part[((size_t)blockIdx.x * NF + threadIdx.x) * 2 + PASS] = t;
   }
 }
 
@@ -379,20 +379,22 @@ __global__ void __launch_bounds__(kStdBlock) k_standardize(float* x, int64_t row
     base[(size_t)r * cols] = (float)(((double)base[(size_t)r * cols] - mu) / sd);
 }
 
-__global__ void k_colstats_final(const double* part, int64_t rows, float* mean, float* sd) {
+__global__ void k_colstats_mean(const double* part, int64_t rows, double* mu) {
   const int c = threadIdx.x;
   if (c >= NF) return;
-  double s = 0.0, q = 0.0;
-  for (int k = 0; k < kStatGrid; ++k) {
-    s += part[((size_t)k * NF + c) * 2 + 0];
-    q += part[((size_t)k * NF + c) * 2 + 1];
-  }
-  const double mu = s / (double)rows;
-  double var = q / (double)rows - mu * mu;
-  if (var < 0.0) var = 0.0;
-  double sdv = sqrt(var);
+  double s = 0.0;
+  for (int k = 0; k < kStatGrid; ++k) s += part[((size_t)k * NF + c) * 2 + 0];
+  mu[c] = s / (double)rows;
+}
+
+__global__ void k_colstats_final(const double* part, int64_t rows, const double* mu, float* mean, float* sd) {
+  const int c = threadIdx.x;
+  if (c >= NF) return;
+  double q = 0.0;
+  for (int k = 0; k < kStatGrid; ++k) q += part[((size_t)k * NF + c) * 2 + 1];
+  double sdv = sqrt(q / (double)rows);
   if (sdv < 1e-6) sdv = 1e-6;
-  mean[c] = (float)mu;
+  mean[c] = (float)mu[c];
   sd[c] = (float)sdv;
 }
 
@@ -449,6 +451,11 @@ __global__ void k_clone(const int32_t* order, int n_rep, int64_t n, int8_t* spin
 __global__ void k_final_cut_score(const float* gain, const float* feat, int64_t n, double w_over_e, float* score) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) score[i] = (float)(0.5 * (w_over_e - (double)feat[i * NF]) + (double)gain[i]);
+}
+
+__global__ void k_cut_labels(const int64_t* final_cut, const int64_t* now_cut, int64_t n, double scale, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)((double)(final_cut[i] - (now_cut ? now_cut[i] : 0)) * scale);
 }
 
 __global__ void k_energy_score(const int64_t* energy, int64_t n, float* score) {
@@ -568,11 +575,17 @@ int ising_feature_stats(const float* x, int64_t rows, float* mean, float* std, v
   if (!x || !mean || !std) return fail(ISING_E_ARG, "NULL buffer");
   hipStream_t st = (hipStream_t)stream;
   double* part = nullptr;
-  const size_t bytes = sizeof(double) * ising::kStatGrid * ISING_N_FEATURES * 2;
+  const size_t n_part = (size_t)ising::kStatGrid * ISING_N_FEATURES * 2;
+  const size_t bytes = sizeof(double) * (n_part + ISING_N_FEATURES);
   hipError_t e = hipMallocAsync((void**)&part, bytes, st);
   if (e != hipSuccess) return fail(ISING_E_NOMEM, "stats workspace: %s", hipGetErrorString(e));
-  hipLaunchKernelGGL(ising::k_colstats_partial, dim3(ising::kStatGrid), dim3(ising::kStatBlock), 0, st, x, rows, part);
-  hipLaunchKernelGGL(ising::k_colstats_final, dim3(1), dim3(64), 0, st, part, rows, mean, std);
+  double* mu = part + n_part;
+  hipLaunchKernelGGL(ising::k_colstats_partial<0>, dim3(ising::kStatGrid), dim3(ising::kStatBlock), 0, st, x, rows,
+                     (const double*)nullptr, part);
+  hipLaunchKernelGGL(ising::k_colstats_mean, dim3(1), dim3(64), 0, st, part, rows, mu);
+  hipLaunchKernelGGL(ising::k_colstats_partial<1>, dim3(ising::kStatGrid), dim3(ising::kStatBlock), 0, st, x, rows,
+                     (const double*)mu, part);
+  hipLaunchKernelGGL(ising::k_colstats_final, dim3(1), dim3(64), 0, st, part, rows, (const double*)mu, mean, std);
   e = hipGetLastError();
   (void)hipFreeAsync(part, st);
   return e == hipSuccess ? ISING_OK : fail_hip(e, "feature stats launch");
@@ -633,6 +646,18 @@ int ising_final_cut_score(const ising_graph* g, const float* gain, const float* 
                      (hipStream_t)stream, gain, features, n_replicas, w_over_e, score);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? ISING_OK : fail_hip(e, "final cut score launch");
+}
+
+int ising_cut_labels(const int64_t* final_cut, const int64_t* now_cut, int64_t n_replicas, double scale, float* out,
+                     void* stream) {
+  if (n_replicas < 0 || n_replicas > INT32_MAX) return fail(ISING_E_ARG, "n_replicas out of range");
+  if (!std::isfinite(scale)) return fail(ISING_E_ARG, "scale must be finite");
+  if (n_replicas == 0) return ISING_OK;
+  if (!final_cut || !out) return fail(ISING_E_ARG, "NULL buffer");
+  hipLaunchKernelGGL(ising::k_cut_labels, dim3((unsigned)((n_replicas + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     final_cut, now_cut, n_replicas, scale, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? ISING_OK : fail_hip(e, "cut labels launch");
 }
 
 int ising_energy_score(const int64_t* energy, int64_t n_replicas, float* score, void* stream) {

@@ -52,28 +52,6 @@ struct BpArgs {
   int32_t flush_every;  // sweeps between flushes of the 8-bit flip counters
 };
 
-// Bit-sliced population count of DEG one-bit inputs per lane: u = u0 + 2 u1 + 4 u2.
-template <int DEG>
-__device__ __forceinline__ void bond_count(const uint32_t* x, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
-  if (DEG == 4) {
-    const uint32_t s1 = x[0] ^ x[1], c1 = x[0] & x[1];
-    const uint32_t s2 = x[2] ^ x[3], c2 = x[2] & x[3];
-    u0 = s1 ^ s2;
-    const uint32_t k = s1 & s2;
-    u1 = xor3(c1, c2, k);
-    u2 = (c1 & c2) | (k & (c1 | c2));
-  } else {
-    const uint32_t s1 = xor3(x[0], x[1], x[2]);
-    const uint32_t c1 = (x[0] & x[1]) | (x[2] & (x[0] | x[1]));
-    const uint32_t s2 = xor3(x[3], x[4], x[5]);
-    const uint32_t c2 = (x[3] & x[4]) | (x[5] & (x[3] | x[4]));
-    u0 = s1 ^ s2;
-    const uint32_t k = s1 & s2;
-    u1 = xor3(c1, c2, k);
-    u2 = (c1 & c2) | (k & (c1 | c2));
-  }
-}
-
 // Per-lane value of a bit-sliced counter of NPLANES planes, added to LDS
 // counters dst[0..31] (lanes below nvalid only): summed over the wave first,
 // then one atomic per wave and counter.  Every thread of the block calls it.
@@ -137,7 +115,7 @@ __device__ __forceinline__ uint32_t bp_decide(const uint32_t* x, uint64_t seed, 
                                               uint32_t& n_blocks, uint32_t& n_draws) {
   constexpr int DEG = 2 * NDIM;
   uint32_t u0, u1, u2;
-  bond_count<DEG>(x, u0, u1, u2);
+  bond_count3<DEG>(x, u0, u1, u2);
   uint32_t acc, k1, k2, k3 = 0u;
   if (NDIM == 2) {
     acc = u1 | u2;        // u >= 2

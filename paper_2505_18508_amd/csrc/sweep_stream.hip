@@ -33,27 +33,6 @@ struct StreamArgs {
   int32_t n_replicas, replica_offset, groups;
 };
 
-template <int DEG>
-__device__ __forceinline__ void count_bonds(const uint32_t* x, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
-  if (DEG == 4) {
-    const uint32_t s1 = x[0] ^ x[1], c1 = x[0] & x[1];
-    const uint32_t s2 = x[2] ^ x[3], c2 = x[2] & x[3];
-    u0 = s1 ^ s2;
-    const uint32_t k = s1 & s2;
-    u1 = xor3(c1, c2, k);
-    u2 = (c1 & c2) | (k & (c1 | c2));
-  } else {
-    const uint32_t s1 = xor3(x[0], x[1], x[2]);
-    const uint32_t c1 = (x[0] & x[1]) | (x[2] & (x[0] | x[1]));
-    const uint32_t s2 = xor3(x[3], x[4], x[5]);
-    const uint32_t c2 = (x[3] & x[4]) | (x[5] & (x[3] | x[4]));
-    u0 = s1 ^ s2;
-    const uint32_t k = s1 & s2;
-    u1 = xor3(c1, c2, k);
-    u2 = (c1 & c2) | (k & (c1 | c2));
-  }
-}
-
 // One stage of a 32 x 32 bit transpose across the 32 lanes of a half-wave
 // (row = lane, column = bit), the partner being lane ^ J: a lane whose bit J
 // is clear keeps the low J-bit half of every 2J-bit block and takes the
@@ -111,7 +90,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
       x[d] = xor3(s, w[nb[d]], plus);                              // unsatisfied bonds
     }
     uint32_t u0, u1, u2;
-    count_bonds<DEG>(x, u0, u1, u2);
+    bond_count3<DEG>(x, u0, u1, u2);
     uint32_t acc, k1, k2, k3 = 0u;
     if (NDIM == 2) {
       acc = u1 | u2;

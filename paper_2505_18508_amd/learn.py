@@ -20,9 +20,9 @@ import time
 
 import numpy as np
 
-from . import (adam_step, create_graph, cull_clone, energy_score, feature_stats, features, final_cut_score,
-               mlp_forward, mlp_init, mlp_loss_grad, mlp_workspace_floats, new_track, run_trials, schedule_beta,
-               standardize_groups)
+from . import (adam_step, create_graph, cull_clone, cut_labels, energy_score, feature_stats, features,
+               final_cut_score, mlp_forward, mlp_init, mlp_loss_grad, mlp_workspace_floats, new_track, run_trials,
+               schedule_beta, standardize_groups)
 from . import metrics
 
 METHODS = ("plain", "learned", "energy")
@@ -149,15 +149,17 @@ def trajectories(instances, n_replicas, n_sweeps, window, schedule="geometric", 
         if label == "relative":
             X = torch.cat(rows)
             standardize_groups(X, len(rows), R, 16)
-            y = final.to(torch.float32)
+            y = torch.empty(R, dtype=torch.float32, device=final.device)
+            cut_labels(final, y)
             standardize_groups(y, 1, R, 1)
             xs.append(X)
             ys.extend([y] * len(rows))
         else:
             xs.extend(rows)
             for k in range(len(rows)):
-                y = final - cuts[k] if label == "gain" else final
-                ys.append(y.to(torch.float32) / float(g.n_edges))
+                y = torch.empty(R, dtype=torch.float32, device=final.device)
+                cut_labels(final, y, cuts[k] if label == "gain" else None, 1.0 / g.n_edges)
+                ys.append(y)
         g.close()
     return torch.cat(xs), torch.cat(ys)
 

@@ -289,3 +289,21 @@ def test_final_cut_score_matches_oracle(ising):
     ising.final_cut_score(g, dev_tensor(gain), dev_tensor(feats), score)
     ref = olearn.final_cut_score(g.w_total, g.n_edges, gain, feats)
     assert np.allclose(score.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+
+
+def test_cut_labels_match_their_definition(ising):
+    """(final - now) * scale in double, rounded to float once; without now,
+    final * scale."""
+    import torch
+
+    rng = np.random.default_rng(17)
+    R = 3000
+    final = rng.integers(13000, 14000, size=R).astype(np.int64)
+    now = final - rng.integers(0, 200, size=R).astype(np.int64)
+    out = torch.zeros(R, dtype=torch.float32, device="cuda")
+    scale = 1.0 / 40000
+    ising.cut_labels(dev_tensor(final), out, dev_tensor(now), scale)
+    want = ((final - now).astype(np.float64) * scale).astype(np.float32)
+    assert (out.cpu().numpy() == want).all()
+    ising.cut_labels(dev_tensor(final), out)
+    assert (out.cpu().numpy() == final.astype(np.float64).astype(np.float32)).all()
