@@ -49,11 +49,12 @@ def test_learned_culling_beats_plain_and_energy_ranking_on_the_20000_spin_torus(
     assert sum(L) > sum(E)
 
 
-def test_learned_culling_with_raw_features_beats_plain_at_small_scale():
-    """50 x 100 torus, 1,024 replicas, 4,000 sweeps, network on raw features
-    (label "final"): faster to the target than the plain run.  (At this size
-    the energy ranking alone does as well as the network, and raw-feature
-    rankings do not lift every seed's mean end-of-trial cut above plain.)"""
+def test_learned_culling_beats_plain_at_small_scale():
+    """50 x 100 torus, 1,024 replicas, 4,000 sweeps, a ranking every 400
+    sweeps, network trained on 4 other instances: every seed ends with a
+    higher mean end-of-trial cut than the plain run and reaches the target
+    sooner.  (At this size the energy ranking alone does as well as the
+    network.)"""
     import torch
 
     assert torch.cuda.is_available()
@@ -61,9 +62,30 @@ def test_learned_culling_with_raw_features_beats_plain_at_small_scale():
 
     s = experiments.ttt_experiment(dims=(50, 100), weight_seed=3001, R=1024, S=4000, window=400,
                                    run_seeds=(201, 202, 203), train_seeds=(1001, 1002, 1003, 1004), n_traj=4096,
-                                   epochs=20, batch=8192, long_sweeps=4000, label="final", log=print)
+                                   epochs=20, batch=8192, long_sweeps=4000, label="relative", log=print)
     blk = s["targets"]["compared_runs"]
     ttt = {m: blk["methods"][m]["median_TTT_s"] for m in blk["methods"]}
-    print("target", blk["target"], "median TTT (s)", ttt, "energy ranking", ttt["energy"])
+    print("target", blk["target"], "median TTT (s)", ttt)
     assert s["train_loss"][-1] < s["train_loss"][0]
+    assert all(l > p for l, p in zip(_means(s, "learned"), _means(s, "plain")))
     assert math.isfinite(ttt["learned"]) and ttt["learned"] < ttt["plain"]
+
+
+def test_raw_feature_labels_train_and_cull():
+    """The "final" and "gain" labels (raw features z-scored with the training
+    set's statistics) train to a lower loss and run the culled form to the
+    end with valid cuts.  No gain over plain is claimed for them: at this
+    size their rankings are on par with plain annealing."""
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2505_18508_amd import experiments
+
+    for label in ("final", "gain"):
+        s = experiments.ttt_experiment(dims=(50, 100), weight_seed=3001, R=256, S=2000, window=400,
+                                       run_seeds=(201,), train_seeds=(1001, 1002), n_traj=512, epochs=5,
+                                       batch=1024, long_sweeps=2000, label=label, log=print)
+        assert s["train_loss"][-1] < s["train_loss"][0]
+        for m in ("plain", "learned", "energy"):
+            (run,) = s["runs"][m]
+            assert 0 < run["best"] <= s["n_edges"]
