@@ -49,45 +49,84 @@ __device__ __forceinline__ uint32_t transpose_stage(uint32_t x, uint32_t lane, u
   return (hi & upper) | (lo & ~upper);                    // select without a branch
 }
 
-template <int NDIM, bool STATS>
-__global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a, int p, int t) {
+// The draws of a word's 32 replicas against the first LEV thresholds (LEV
+// >= 1; they decrease with k, so the nonzero ones are a prefix): bit j of
+// c_k = (Philox word of replica j) < T_k.
+template <int LEV>
+__device__ __forceinline__ void stream_draws(uint64_t seed, uint32_t ci, uint32_t t, uint32_t quad0, uint32_t T1,
+                                             uint32_t T2, uint32_t T3, uint32_t& c1, uint32_t& c2, uint32_t& c3) {
+#pragma unroll
+  for (int q = 7; q >= 0; --q) {
+    const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
+    lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
+  }
+}
+
+// A thread's strip: column m of K consecutive lines l0 .. l0+K-1 of one
+// plane (fewer for the last strip of a 2-D torus).  Going up the strip, the
+// other colour's word of the line just visited becomes the next line's -y
+// neighbour and its +y neighbour becomes the next line's same-column
+// neighbour, so a visit loads its own word, its weight signs, the x-shift
+// and +y neighbours (and, in 3-D, the +-z ones).  Flips are added into
+// bit-sliced counters fp[0..NP) (count = sum 2^b fp[b]).
+template <int NDIM, bool STATS, int K, int LEV, int NP>
+__device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, int p, uint32_t t, uint32_t strip,
+                                             uint32_t m, uint32_t quad0, uint32_t lanes, uint32_t T1, uint32_t T2,
+                                             uint32_t T3, uint32_t* fp, uint32_t& n_words, uint32_t& n_draws) {
   constexpr int DEG = 2 * NDIM;
   const Lattice& L = a.lat;
-  const int g = blockIdx.y;
-  const uint32_t h = blockIdx.x * kStreamBlock + threadIdx.x;
-  const int r0 = 32 * g;
-  const int nvalid = min(32, a.n_replicas - r0);
-  uint32_t F = 0u;
-  uint32_t n_draws = 0u;
-  const uint32_t* tr = a.thr + (size_t)t * NDIM;
-  const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
-  if (h < (uint32_t)L.half) {
-    const uint32_t hx = (uint32_t)L.hx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz;
-    const uint32_t line = h / hx;  // one division per thread and launch
-    const uint32_t m = h - line * hx;
-    const uint32_t z = NDIM == 2 ? 0u : line / Ly;
-    const uint32_t y = line - z * Ly;
-    const uint32_t o = (p + y + z) & 1u;
-    uint32_t* w = a.words + (size_t)g * L.n;
-    const uint32_t own = (uint32_t)p * (uint32_t)L.half + h;
-    const uint32_t base = (uint32_t)(1 - p) * (uint32_t)L.half + line * hx;  // same line, other colour
-    const uint32_t plane = hx * Ly;
-    uint32_t nb[DEG];
-    nb[0] = base + (o ? (m + 1u == hx ? 0u : m + 1u) : m);
-    nb[1] = base + (o ? m : (m == 0u ? hx - 1u : m - 1u));
-    nb[2] = (y + 1u == Ly) ? base + m + hx - plane : base + m + hx;
-    nb[3] = (y == 0u) ? base + m + plane - hx : base + m - hx;
+  const uint32_t hx = (uint32_t)L.hx, Ly = (uint32_t)L.Ly, Lz = (uint32_t)L.Lz, Lx = (uint32_t)L.Lx;
+  const uint32_t lines = (uint32_t)L.lines, half = (uint32_t)L.half;
+  const uint32_t plane = hx * Ly;
+  const uint32_t l0 = strip * (uint32_t)K;
+  const uint32_t z = NDIM == 2 ? 0u : l0 / Ly;
+  uint32_t y = l0 - z * Ly;
+  const uint32_t m_up = (m + 1u == hx) ? 0u : m + 1u;
+  const uint32_t m_dn = (m == 0u) ? hx - 1u : m - 1u;
+  uint32_t own = (uint32_t)p * half + l0 * hx + m;
+  uint32_t oth = (uint32_t)(1 - p) * half + l0 * hx;  // the other colour's words of line l0
+  uint32_t omask = 0u - (((uint32_t)p + y + z) & 1u);  // all ones where x = 2m + 1 (o = 1)
+  uint32_t ci = l0 * Lx + 2u * m + (omask & 1u);
+  // z neighbours: same offsets for every line of the strip (one plane)
+  const uint32_t dzp = (z + 1u == Lz) ? 0u - (Lz - 1u) * plane : plane;
+  const uint32_t dzm = (z == 0u) ? (Lz - 1u) * plane : 0u - plane;
+  uint32_t ym = w[oth + (y == 0u ? plane - hx : 0u - hx) + m];
+  uint32_t x0 = w[oth + m];
+  // the loads of line k + 1 are issued before line k is decided (software
+  // pipelining): they touch the other colour's words, which this launch
+  // never writes, and the next own word, which line k does not write
+  auto load_line = [&](uint32_t o_own, uint32_t o_oth, uint32_t yy, uint32_t om, uint32_t* v) {
+    v[0] = w[o_oth + (yy + 1u == Ly ? 0u - (Ly - 1u) * hx : hx) + m];  // +y
+    v[1] = w[o_oth + (om ? m_up : m_dn)];                               // x-shift
+    v[2] = w[o_own];                                                    // own word
+    v[3] = a.wbits[o_own];                                              // weight signs
     if (NDIM == 3) {
-      nb[DEG - 2] = (z + 1u == Lz) ? base + m - (Lz - 1u) * plane : base + m + plane;
-      nb[DEG - 1] = (z == 0u) ? base + m + (Lz - 1u) * plane : base + m - plane;
+      v[4] = w[o_oth + dzp + m];
+      v[5] = w[o_oth + dzm + m];
     }
-    const uint32_t s = w[own];
-    const uint32_t wb = a.wbits[own];
+  };
+  uint32_t cur[6], nxt[6];
+  load_line(own, oth, y, omask, cur);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (l0 + (uint32_t)k >= lines) break;
+    const bool more = k + 1 < K && l0 + (uint32_t)k + 1u < lines;
+    if (more) load_line(own + hx, oth + hx, y + 1u, ~omask, nxt);
+    const uint32_t yp = cur[0], xs = cur[1], s = cur[2], wb = cur[3];
+    uint32_t nb[DEG];
+    nb[0] = (omask & xs) | (~omask & x0);  // +x: column m + 1 where o = 1, m where o = 0
+    nb[1] = (omask & x0) | (~omask & xs);  // -x
+    nb[2] = yp;
+    nb[3] = ym;
+    if (NDIM == 3) {
+      nb[DEG - 2] = cur[4];
+      nb[DEG - 1] = cur[5];
+    }
     uint32_t x[DEG];
 #pragma unroll
     for (int d = 0; d < DEG; ++d) {
       const uint32_t plus = ((wb >> d) & 1u) ? 0u : 0xFFFFFFFFu;  // all ones iff w = +1
-      x[d] = xor3(s, w[nb[d]], plus);                              // unsatisfied bonds
+      x[d] = xor3(s, nb[d], plus);                                // unsatisfied bonds
     }
     uint32_t u0, u1, u2;
     bond_count3<DEG>(x, u0, u1, u2);
@@ -102,40 +141,92 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
       k2 = u0 & ~u1 & ~u2;
       k3 = ~(u0 | u1 | u2);
     }
-    uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-    if (T1 != 0u) {
-      const uint32_t ci = line * (uint32_t)L.Lx + 2u * m + o;
-      const uint32_t quad0 = (uint32_t)(a.replica_offset + r0) >> 2;
-      // thresholds decrease with k, so the nonzero ones are a prefix
-      auto draws = [&](auto lev) {
-#pragma unroll
-        for (int q = 7; q >= 0; --q) {
-          const u32x4 r = philox_lane_c0(a.seed, ci, (uint32_t)t, quad0 + (uint32_t)q, kTagMetropolis);
-          lt_shift_in4<decltype(lev)::value>(c1, c2, c3, r.v, T1, T2, T3);
-        }
-      };
-      if (T2 == 0u)
-        draws(std::integral_constant<int, 1>());
-      else if (NDIM == 2 || T3 == 0u)
-        draws(std::integral_constant<int, 2>());
-      else
-        draws(std::integral_constant<int, 3>());
+    uint32_t F = acc;
+    if (LEV > 0) {
+      uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
+      stream_draws<(LEV > 0 ? LEV : 1)>(a.seed, ci, t, quad0, T1, T2, T3, c1, c2, c3);
+      F |= (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u);
       if (STATS) {
-        const uint32_t lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
-        n_draws = __popc((k1 | (T2 ? k2 : 0u) | (T3 ? k3 : 0u)) & lanes);
+        n_words += 1u;
+        n_draws += __popc((k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u)) & lanes);
       }
     }
-    F = acc | (k1 & c1) | (k2 & c2) | (k3 & c3);
-    if (F) w[own] = s ^ F;
-  }
-  if (STATS) {  // block totals of Philox blocks (8 per word) and draws, kept in the block's slot
-    __shared__ uint32_t ws[kStreamBlock / 64][2];
-    const uint32_t words_here = (uint32_t)__popcll(__ballot(h < (uint32_t)L.half && T1 != 0u));
-    uint32_t d = n_draws;
+    w[own] = s ^ F;
+    uint32_t c = F;  // add F into the bit-sliced counters
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    for (int b = 0; b < NP; ++b) {
+      const uint32_t carry = fp[b] & c;
+      fp[b] ^= c;
+      c = carry;
+    }
+    ym = x0;
+    x0 = yp;
+    own += hx;
+    oth += hx;
+    y += 1u;
+    omask = ~omask;
+    ci += Lx + ((omask & 2u) - 1u);  // next line, x parity flipped: +Lx +1 if o becomes 1, +Lx -1 if 0
+#pragma unroll
+    for (int e = 0; e < 6; ++e) cur[e] = nxt[e];
+  }
+}
+
+// One launch per colour half-sweep.  Each thread walks a strip of K lines
+// (stream_strip); blocks are taken in an XCD-aware order.
+template <int NDIM, bool STATS, int K>
+__global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a, int p, int t) {
+  constexpr int NP = K <= 1 ? 1 : K <= 3 ? 2 : 3;  // planes of a count up to K
+  const Lattice& L = a.lat;
+  // The dispatcher deals consecutive blocks to the 8 XCDs in turn; the blocks
+  // one XCD receives take consecutive logical indices, so the strips that
+  // share rows of words (neighbouring lines and columns) meet in one L2.
+  const uint32_t nblk = gridDim.x * gridDim.y;
+  const uint32_t lin = blockIdx.x + blockIdx.y * gridDim.x;
+  const uint32_t per = nblk / 8u, rem = nblk % 8u, xcd = lin % 8u;
+  const uint32_t logical = xcd * per + (xcd < rem ? xcd : rem) + lin / 8u;
+  const int g = (int)(logical / gridDim.x);
+  const uint32_t bx = logical - (uint32_t)g * gridDim.x;
+  const uint32_t hx = (uint32_t)L.hx;
+  const uint32_t n_items = hx * (((uint32_t)L.lines + (uint32_t)K - 1u) / (uint32_t)K);
+  const uint32_t item = bx * kStreamBlock + threadIdx.x;
+  const int r0 = 32 * g;
+  const int nvalid = min(32, a.n_replicas - r0);
+  const uint32_t lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
+  const uint32_t* tr = a.thr + (size_t)t * NDIM;
+  const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
+  const int lev = T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
+  uint32_t fp[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) fp[b] = 0u;
+  uint32_t n_words = 0u, n_draws = 0u;
+  if (item < n_items) {
+    const uint32_t strip = item / hx;
+    const uint32_t m = item - strip * hx;
+    uint32_t* w = a.words + (size_t)g * L.n;
+    const uint32_t quad0 = (uint32_t)(a.replica_offset + r0) >> 2;
+    if (lev == 0)
+      stream_strip<NDIM, STATS, K, 0, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
+                                          n_draws);
+    else if (lev == 1)
+      stream_strip<NDIM, STATS, K, 1, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
+                                          n_draws);
+    else if (NDIM == 2 || lev == 2)
+      stream_strip<NDIM, STATS, K, 2, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
+                                          n_draws);
+    else
+      stream_strip<NDIM, STATS, K, 3, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
+                                          n_draws);
+  }
+  if (STATS) {  // block totals of Philox blocks (8 per word that drew) and draws, kept in the block's slot
+    __shared__ uint32_t ws[kStreamBlock / 64][2];
+    uint32_t d = n_draws, nw = n_words;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      d += __shfl_xor(d, off, 64);
+      nw += __shfl_xor(nw, off, 64);
+    }
     if ((threadIdx.x & 63) == 0) {
-      ws[threadIdx.x >> 6][0] = words_here;
+      ws[threadIdx.x >> 6][0] = nw;
       ws[threadIdx.x >> 6][1] = d;
     }
     __syncthreads();
@@ -144,30 +235,35 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
 #pragma unroll
       for (int k = 0; k < kStreamBlock / 64; ++k) c += ws[k][threadIdx.x];
       if (threadIdx.x == 0) c *= 8ull;
-      a.spart[((size_t)g * gridDim.x + blockIdx.x) * 2 + threadIdx.x] += c;
+      a.spart[((size_t)g * gridDim.x + bx) * 2 + threadIdx.x] += c;
     }
   }
   // flips per replica: transposing the 32 x 32 bit matrix of each half-wave
-  // (row = lane, column = replica bit of F) leaves in lane j the half-wave's
-  // flips of replica j as the bits of one word; the block adds its
-  // half-waves and keeps a running total in its own slot (the same block
-  // index owns the same slot in every launch: no atomics)
+  // (row = lane, column = replica bit) of every counter plane leaves in lane j
+  // the half-wave's counts of replica j; the block adds its half-waves and
+  // keeps a running total in its own slot (the same logical block owns the
+  // same slot in every launch: no atomics)
   if (a.part) {
     __shared__ uint32_t wc[kStreamBlock / 32][32];
     const uint32_t lane = threadIdx.x & 31u;
-    uint32_t x = F;
-    x = transpose_stage<16>(x, lane, 0x0000FFFFu);
-    x = transpose_stage<8>(x, lane, 0x00FF00FFu);
-    x = transpose_stage<4>(x, lane, 0x0F0F0F0Fu);
-    x = transpose_stage<2>(x, lane, 0x33333333u);
-    x = transpose_stage<1>(x, lane, 0x55555555u);
-    wc[threadIdx.x >> 5][lane] = (uint32_t)__popc(x);
+    uint32_t cnt = 0u;
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+      uint32_t x = fp[b];
+      x = transpose_stage<16>(x, lane, 0x0000FFFFu);
+      x = transpose_stage<8>(x, lane, 0x00FF00FFu);
+      x = transpose_stage<4>(x, lane, 0x0F0F0F0Fu);
+      x = transpose_stage<2>(x, lane, 0x33333333u);
+      x = transpose_stage<1>(x, lane, 0x55555555u);
+      cnt += (uint32_t)__popc(x) << b;
+    }
+    wc[threadIdx.x >> 5][lane] = cnt;
     __syncthreads();
     if (threadIdx.x < 32) {
       uint32_t c = 0u;
 #pragma unroll
       for (int k = 0; k < kStreamBlock / 32; ++k) c += wc[k][threadIdx.x];
-      uint32_t* slot = a.part + ((size_t)g * gridDim.x + blockIdx.x) * 32 + threadIdx.x;
+      uint32_t* slot = a.part + ((size_t)g * gridDim.x + bx) * 32 + threadIdx.x;
       *slot += c;
     }
   }
@@ -277,14 +373,32 @@ __global__ void k_mark_invalid(const uint32_t* bad, int32_t R, int64_t* cut, int
 
 }  // namespace
 
-static int stream_blocks_x(const Lattice& L) { return (L.half + kStreamBlock - 1) / kStreamBlock; }
+// Lines per thread: the largest of 4, 2 whose strips still give at least
+// 16 waves per CU of a 256-CU device over all groups (and, in 3-D, that
+// divides Ly, so that no strip leaves its plane); else 1.  Longer strips
+// hold more loads in flight than registers allow at full occupancy.
+static int stream_lines_per_thread(const Lattice& L, int groups) {
+  for (int k = 4; k > 1; k >>= 1) {
+    if (L.ndim == 3 && L.Ly % k != 0) continue;
+    const int64_t strips = ((int64_t)L.lines + k - 1) / k;
+    if ((int64_t)L.hx * strips * groups >= (int64_t)256 * 16 * 64) return k;
+  }
+  return 1;
+}
+
+static int stream_blocks_x(const Lattice& L, int groups) {
+  const int k = stream_lines_per_thread(L, groups);
+  const int64_t items = (int64_t)L.hx * (((int64_t)L.lines + k - 1) / k);
+  return (int)((items + kStreamBlock - 1) / kStreamBlock);
+}
 
 size_t stream_words_bytes(const Lattice& L, int n_replicas) {
   return sizeof(uint32_t) * (size_t)L.n * (size_t)((n_replicas + 31) / 32);
 }
 
 size_t stream_part_bytes(const Lattice& L, int n_replicas, bool flips, bool stats) {
-  const size_t slots = (size_t)stream_blocks_x(L) * (size_t)((n_replicas + 31) / 32);
+  const int groups = (n_replicas + 31) / 32;
+  const size_t slots = (size_t)stream_blocks_x(L, groups) * (size_t)groups;
   return (flips ? sizeof(uint32_t) * 32 * slots : 0) + (stats ? sizeof(unsigned long long) * 2 * slots : 0);
 }
 
@@ -292,7 +406,8 @@ hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint3
                                uint32_t* part, hipStream_t stream, int64_t* cut_part) {
   const Lattice& L = g->lat;
   const int groups = (s.n_replicas + 31) / 32;
-  const int bx = stream_blocks_x(L);
+  const int bx = stream_blocks_x(L, groups);
+  const int K = stream_lines_per_thread(L, groups);
   const dim3 site_grid((unsigned)((L.n + 255) / 256), (unsigned)groups);
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, stream, bad, (int64_t)groups);
   const int64_t n_slots = (int64_t)bx * groups;
@@ -321,16 +436,25 @@ hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint3
   a.replica_offset = s.replica_offset;
   a.groups = groups;
   const dim3 grid((unsigned)bx, (unsigned)groups);
-  for (int t = s.t_begin; t < s.t_end; ++t) {
-    for (int p = 0; p < 2; ++p) {
-      if (g->ndim == 2) {
-        if (s.stats) hipLaunchKernelGGL((k_halfsweep_stream<2, true>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
-        else hipLaunchKernelGGL((k_halfsweep_stream<2, false>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
-      } else {
-        if (s.stats) hipLaunchKernelGGL((k_halfsweep_stream<3, true>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
-        else hipLaunchKernelGGL((k_halfsweep_stream<3, false>), grid, dim3(kStreamBlock), 0, stream, a, p, t);
-      }
-    }
+  auto go = [&](auto kernel) {
+    for (int t = s.t_begin; t < s.t_end; ++t)
+      for (int p = 0; p < 2; ++p) hipLaunchKernelGGL(kernel, grid, dim3(kStreamBlock), 0, stream, a, p, t);
+  };
+  auto pick = [&](auto nd, auto st) {
+    constexpr int ND = decltype(nd)::value;
+    constexpr bool ST = decltype(st)::value;
+    if (K == 4) go(k_halfsweep_stream<ND, ST, 4>);
+    else if (K == 2) go(k_halfsweep_stream<ND, ST, 2>);
+    else go(k_halfsweep_stream<ND, ST, 1>);
+  };
+  using ND2 = std::integral_constant<int, 2>;
+  using ND3 = std::integral_constant<int, 3>;
+  using STY = std::integral_constant<bool, true>;
+  using STN = std::integral_constant<bool, false>;
+  if (g->ndim == 2) {
+    if (s.stats) pick(ND2(), STY()); else pick(ND2(), STN());
+  } else {
+    if (s.stats) pick(ND3(), STY()); else pick(ND3(), STN());
   }
   hipLaunchKernelGGL(k_unpack, site_grid, dim3(256), 0, stream, L, words, s.n_replicas, s.spins);
   if (s.flips)
