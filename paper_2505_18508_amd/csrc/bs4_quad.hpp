@@ -169,13 +169,21 @@ __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t 
     const uint32_t cib = ci0 + (uint32_t)(j - 1) * Lx + q;
     u32x4 ra, rb;
     philox_lane_c0_x2(seed, cia, cib, t, quad, kTagMetropolis, ra, rb);
-    if (PT) {
-      lt_shift_in4<LEV>(c1, c2, c3, ra.v, th.T[0], th.T[1], th.T[2]);
-      lt_shift_in4<LEV>(c1, c2, c3, rb.v, th.T[0], th.T[1], th.T[2]);
-    } else {
-      lt_shift_in4<LEV>(c1, c2, c3, ra.v, T1, T2, T3);
-      lt_shift_in4<LEV>(c1, c2, c3, rb.v, T1, T2, T3);
+    // the first compares of the word start the chains
+    const uint32_t* t1 = th.T[0];
+    const uint32_t* t2 = th.T[1];
+    const uint32_t* t3 = th.T[2];
+    const uint32_t s1[4] = {T1, T1, T1, T1}, s2[4] = {T2, T2, T2, T2}, s3[4] = {T3, T3, T3, T3};
+    if (!PT) {
+      t1 = s1;
+      t2 = s2;
+      t3 = s3;
     }
+    if (j == 3)
+      lt_shift_in4<LEV, true>(c1, c2, c3, ra.v, t1, t2, t3);
+    else
+      lt_shift_in4<LEV>(c1, c2, c3, ra.v, t1, t2, t3);
+    lt_shift_in4<LEV>(c1, c2, c3, rb.v, t1, t2, t3);
   }
 }
 
@@ -242,20 +250,42 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
   }
 }
 
-// bs4_half for the number of nonzero threshold levels of this sweep
-// (the largest k with some T_k != 0; thresholds decrease with k).
-template <int NDIM, int P, bool FLIPS, bool STATS, bool PT, bool PART>
-__device__ __forceinline__ void bs4_half_lev(int lev, char* lds, const Bs4Walk& wk, const Bs4Args& a, int t,
-                                             uint32_t quad, const QuadThr& th, uint32_t T1, uint32_t T2, uint32_t T3,
-                                             uint32_t valid16, uint32_t* fl, uint32_t& n_blocks, uint32_t& n_draws) {
-  if (lev == 0)
-    bs4_half<NDIM, P, 0, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
-  else if (lev == 1)
-    bs4_half<NDIM, P, 1, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
-  else if (NDIM == 2 || lev == 2)
-    bs4_half<NDIM, P, 2, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
-  else
-    bs4_half<NDIM, P, 3, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks, n_draws);
+// Number of leading nonzero threshold levels of a sweep (thresholds
+// decrease with k, so the first zero ends the prefix).
+template <int NDIM>
+__device__ __forceinline__ int sweep_levels(uint32_t T1, uint32_t T2, uint32_t T3) {
+  return T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
+}
+
+// Sweeps t, t + 1, ... of the window while their number of nonzero levels
+// is LEV (under PT the replicas' fixed thresholds: every sweep); returns the
+// first sweep not run.  The level is the same for every thread of the block,
+// so all of them leave at the same sweep and meet the same barriers.  One
+// loop per level keeps the flip counters in the same registers from sweep to
+// sweep; they move only where the level changes.
+template <int NDIM, int LEV, bool FLIPS, bool STATS, bool PT, bool PART>
+__device__ __forceinline__ int bs4_sweeps(int t, bool active, char* lds, const Bs4Walk& wk, const Bs4Args& a,
+                                          uint32_t quad, const QuadThr& th, uint32_t valid16, uint32_t* fl,
+                                          uint32_t& n_blocks, uint32_t& n_draws) {
+  for (; t < a.t_end; ++t) {
+    uint32_t T1 = 0u, T2 = 0u, T3 = 0u;
+    if (!PT) {
+      const uint32_t* tr = a.thr + (size_t)t * NDIM;
+      T1 = tr[0];
+      T2 = tr[1];
+      T3 = NDIM == 3 ? tr[2] : 0u;
+      if (sweep_levels<NDIM>(T1, T2, T3) != LEV) break;
+    }
+    if (active)
+      bs4_half<NDIM, 0, LEV, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks,
+                                                     n_draws);
+    __syncthreads();
+    if (active)
+      bs4_half<NDIM, 1, LEV, FLIPS, STATS, PT, PART>(lds, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks,
+                                                     n_draws);
+    __syncthreads();
+  }
+  return t;
 }
 
 // One replica quad (local replicas r0 .. r0+3) for the window of a.  Called
@@ -386,23 +416,21 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
         th.T[k][b] = (k < NDIM && b < nvalid) ? a.rep_thr[(size_t)(r0 + b) * NDIM + k] : 0u;
     quad_thr_finish(th);
   }
-  for (int t = a.t_begin; t < a.t_end; ++t) {
-    uint32_t T1 = 0u, T2 = 0u, T3 = 0u;
+  int t = a.t_begin;
+  while (t < a.t_end) {
+    int lev = th.lev;
     if (!PT) {
       const uint32_t* tr = a.thr + (size_t)t * NDIM;
-      T1 = tr[0];
-      T2 = tr[1];
-      T3 = NDIM == 3 ? tr[2] : 0u;
+      lev = sweep_levels<NDIM>(tr[0], tr[1], NDIM == 3 ? tr[2] : 0u);
     }
-    const int lev = PT ? th.lev : T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
-    if (active)
-      bs4_half_lev<NDIM, 0, FLIPS, STATS, PT, PART>(lev, lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks,
-                                                    n_draws);
-    __syncthreads();
-    if (active)
-      bs4_half_lev<NDIM, 1, FLIPS, STATS, PT, PART>(lev, lb, wk, a, t, quad, th, T1, T2, T3, valid16, fl, n_blocks,
-                                                    n_draws);
-    __syncthreads();
+    if (lev == 0)
+      t = bs4_sweeps<NDIM, 0, FLIPS, STATS, PT, PART>(t, active, lb, wk, a, quad, th, valid16, fl, n_blocks, n_draws);
+    else if (lev == 1)
+      t = bs4_sweeps<NDIM, 1, FLIPS, STATS, PT, PART>(t, active, lb, wk, a, quad, th, valid16, fl, n_blocks, n_draws);
+    else if (NDIM == 2 || lev == 2)
+      t = bs4_sweeps<NDIM, 2, FLIPS, STATS, PT, PART>(t, active, lb, wk, a, quad, th, valid16, fl, n_blocks, n_draws);
+    else
+      t = bs4_sweeps<NDIM, 3, FLIPS, STATS, PT, PART>(t, active, lb, wk, a, quad, th, valid16, fl, n_blocks, n_draws);
   }
 
   // ---- unsatisfied bonds of the colour-0 sites: energy -----------------------

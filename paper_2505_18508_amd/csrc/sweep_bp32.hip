@@ -91,7 +91,10 @@ __device__ __forceinline__ void draw_compare(uint64_t seed, uint32_t ci, uint32_
 #pragma unroll
   for (int q = 7; q >= 0; --q) {
     const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-    lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
+    if (q == 7)
+      lt_shift_in4<LEV, true>(c1, c2, c3, r.v, T1, T2, T3);
+    else
+      lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
   }
 }
 
