@@ -31,6 +31,13 @@ __device__ __forceinline__ void bond_count3(const uint32_t* x, uint32_t& u0, uin
   }
 }
 
+// Number of leading nonzero threshold levels of a sweep (thresholds
+// decrease with k, so the first zero ends the prefix).
+template <int NDIM>
+__device__ __forceinline__ int sweep_levels(uint32_t T1, uint32_t T2, uint32_t T3) {
+  return T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
+}
+
 // The four words of one Philox block shifted into LEV compare chains at once
 // (word 3 first), word b against its own thresholds T_k[b] (the four
 // replicas of a quad may run at different temperatures; all are uniform

@@ -250,13 +250,6 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
   }
 }
 
-// Number of leading nonzero threshold levels of a sweep (thresholds
-// decrease with k, so the first zero ends the prefix).
-template <int NDIM>
-__device__ __forceinline__ int sweep_levels(uint32_t T1, uint32_t T2, uint32_t T3) {
-  return T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
-}
-
 // Sweeps t, t + 1, ... of the window while their number of nonzero levels
 // is LEV (under PT the replicas' fixed thresholds: every sweep); returns the
 // first sweep not run.  The level is the same for every thread of the block,

@@ -83,6 +83,22 @@ __device__ __forceinline__ void add_planes(uint32_t* planes, uint32_t x) {
   }
 }
 
+// Add two bit vectors at once: a full adder on the lowest plane (sum = xor
+// of the three, carry = their majority), then the carry rippled upwards --
+// one ripple for two vectors.
+template <int NPLANES>
+__device__ __forceinline__ void add_planes2(uint32_t* planes, uint32_t a, uint32_t b) {
+  const uint32_t p0 = planes[0];
+  planes[0] = xor3(p0, a, b);
+  uint32_t c = __builtin_amdgcn_bitop3_b32(p0, a, b, 0xE8);  // majority
+#pragma unroll
+  for (int k = 1; k < NPLANES; ++k) {
+    const uint32_t n = planes[k] & c;
+    planes[k] ^= c;
+    c = n;
+  }
+}
+
 // Threshold compares of the 32 replicas of a site word against the first LEV
 // thresholds; bit j of c[k] = (Philox word of replica j) < T_{k+1}.
 template <int LEV>
@@ -179,19 +195,32 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
       x[3] = xor3(s, p_nb[dym], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 3, 1));
       const uint32_t F = bp_decide<NDIM, LEV, STATS>(x, seed, ci, t, quad0, T1, T2, T3, valid_lanes, n_blocks, n_draws);
       *p_own = s ^ F;
-      if (FLIPS) add_planes<8>(fplanes, F);
       p_own += step;
       p_wl += step;
       p_nb += step;
       ci += w.ci_step;
+      return F;
     };
-    // first line
-    visit(w.y0 + 1u == w.Ly ? w.dyp_wrap : w.row, w.y0 == 0u ? w.dym_wrap : 0u - w.row);
-    if (n_lines >= 2u) {
-      for (uint32_t k = 2u; k < n_lines; ++k) visit(w.row, 0u - w.row);
-      const uint32_t y_last = w.y0 + (n_lines - 1u) * w.lp;
-      visit(y_last + 1u == w.Ly ? w.dyp_wrap : w.row, 0u - w.row);
+    // first line; its flips are counted with the last line's
+    const uint32_t F_first = visit(w.y0 + 1u == w.Ly ? w.dyp_wrap : w.row, w.y0 == 0u ? w.dym_wrap : 0u - w.row);
+    if (n_lines == 1u) {
+      if (FLIPS) add_planes<8>(fplanes, F_first);
+      return;
     }
+    // middle lines two at a time, their flips added as a pair
+    const uint32_t n_mid = n_lines - 2u;
+    for (uint32_t k = 0u; k < n_mid / 2u; ++k) {
+      const uint32_t Fa = visit(w.row, 0u - w.row);
+      const uint32_t Fb = visit(w.row, 0u - w.row);
+      if (FLIPS) add_planes2<8>(fplanes, Fa, Fb);
+    }
+    if (n_mid & 1u) {
+      const uint32_t F = visit(w.row, 0u - w.row);
+      if (FLIPS) add_planes<8>(fplanes, F);
+    }
+    const uint32_t y_last = w.y0 + (n_lines - 1u) * w.lp;
+    const uint32_t F_last = visit(y_last + 1u == w.Ly ? w.dyp_wrap : w.row, 0u - w.row);
+    if (FLIPS) add_planes2<8>(fplanes, F_first, F_last);
     return;
   }
   uint32_t ci0 = w.line0 * w.Lx + 2u * w.m;
@@ -232,23 +261,47 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
   }
 }
 
+// Sweeps t, t + 1, ... of the window while their number of nonzero
+// threshold levels is LEV; returns the first sweep not run.  The levels are
+// the schedule's, the same for every thread of the block, so all of them
+// leave at the same sweep and meet the same barriers.  One loop per level
+// keeps the flip-counter planes in the same registers from sweep to sweep.
+template <int NDIM, int LEV, bool FLIPS, bool STATS, bool EVEN2D>
+__device__ __forceinline__ int bp_sweeps(int t, const BpArgs& a, bool active, uint32_t* lds, const uint8_t* wl,
+                                         const BpWalk& w, uint32_t quad0, uint32_t valid_lanes, uint32_t* fplanes,
+                                         uint32_t* extra, int nvalid, uint32_t& n_blocks, uint32_t& n_draws) {
+  for (; t < a.t_end; ++t) {
+    const uint32_t* tr = a.thr + (size_t)t * NDIM;
+    const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
+    if (sweep_levels<NDIM>(T1, T2, T3) != LEV) break;
+    for (uint32_t p = 0; p < 2u; ++p) {
+      if (active)
+        bp_half_sweep<NDIM, LEV, FLIPS, STATS, EVEN2D>(lds, wl, w, p, a.seed, (uint32_t)t, quad0, T1, T2, T3,
+                                                       valid_lanes, fplanes, n_blocks, n_draws);
+      __syncthreads();
+    }
+    if (FLIPS && ((t - a.t_begin) % a.flush_every == a.flush_every - 1 || t + 1 == a.t_end))
+      flush_planes<8>(fplanes, extra, nvalid);
+  }
+  return t;
+}
+
 template <int NDIM, bool FLIPS, bool STATS, bool EVEN2D>
-__device__ __forceinline__ void bp_half_sweep_lev(int lev, uint32_t* lds, const uint8_t* wl, const BpWalk& w, uint32_t p,
-                                                  uint64_t seed, uint32_t t, uint32_t quad0, uint32_t T1, uint32_t T2,
-                                                  uint32_t T3, uint32_t valid_lanes, uint32_t* fplanes,
-                                                  uint32_t& n_blocks, uint32_t& n_draws) {
+__device__ __forceinline__ int bp_sweeps_lev(int lev, int t, const BpArgs& a, bool active, uint32_t* lds,
+                                             const uint8_t* wl, const BpWalk& w, uint32_t quad0, uint32_t valid_lanes,
+                                             uint32_t* fplanes, uint32_t* extra, int nvalid, uint32_t& n_blocks,
+                                             uint32_t& n_draws) {
   if (lev == 0)
-    bp_half_sweep<NDIM, 0, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
-                                                 n_blocks, n_draws);
-  else if (lev == 1)
-    bp_half_sweep<NDIM, 1, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
-                                                 n_blocks, n_draws);
-  else if (NDIM == 2 || lev == 2)
-    bp_half_sweep<NDIM, 2, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
-                                                 n_blocks, n_draws);
-  else
-    bp_half_sweep<NDIM, 3, FLIPS, STATS, EVEN2D>(lds, wl, w, p, seed, t, quad0, T1, T2, T3, valid_lanes, fplanes,
-                                                 n_blocks, n_draws);
+    return bp_sweeps<NDIM, 0, FLIPS, STATS, EVEN2D>(t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
+                                                    nvalid, n_blocks, n_draws);
+  if (lev == 1)
+    return bp_sweeps<NDIM, 1, FLIPS, STATS, EVEN2D>(t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
+                                                    nvalid, n_blocks, n_draws);
+  if (NDIM == 2 || lev == 2)
+    return bp_sweeps<NDIM, 2, FLIPS, STATS, EVEN2D>(t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
+                                                    nvalid, n_blocks, n_draws);
+  return bp_sweeps<NDIM, 3, FLIPS, STATS, EVEN2D>(t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
+                                                  nvalid, n_blocks, n_draws);
 }
 
 template <int NDIM, bool FLIPS, bool STATS>
@@ -333,23 +386,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
   uint32_t n_blocks = 0u, n_draws = 0u;
   const uint32_t valid_lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
 
-  for (int t = a.t_begin; t < a.t_end; ++t) {
+  int t = a.t_begin;
+  while (t < a.t_end) {
     const uint32_t* tr = a.thr + (size_t)t * NDIM;
-    const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
-    const int lev = T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
-    for (uint32_t p = 0; p < 2u; ++p) {
-      if (active) {
-        if (even2d)
-          bp_half_sweep_lev<NDIM, FLIPS, STATS, true>(lev, lds, wl, w, p, a.seed, (uint32_t)t, quad0, T1, T2, T3,
-                                                      valid_lanes, fplanes, n_blocks, n_draws);
-        else
-          bp_half_sweep_lev<NDIM, FLIPS, STATS, false>(lev, lds, wl, w, p, a.seed, (uint32_t)t, quad0, T1, T2, T3,
-                                                       valid_lanes, fplanes, n_blocks, n_draws);
-      }
-      __syncthreads();
-    }
-    if (FLIPS && ((t - a.t_begin) % a.flush_every == a.flush_every - 1 || t + 1 == a.t_end))
-      flush_planes<8>(fplanes, extra, nvalid);
+    const int lev = sweep_levels<NDIM>(tr[0], tr[1], NDIM == 3 ? tr[2] : 0u);
+    if (even2d)
+      t = bp_sweeps_lev<NDIM, FLIPS, STATS, true>(lev, t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
+                                                  nvalid, n_blocks, n_draws);
+    else
+      t = bp_sweeps_lev<NDIM, FLIPS, STATS, false>(lev, t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
+                                                   nvalid, n_blocks, n_draws);
   }
 
   // ---- unsatisfied bonds along +x, +y (+z): energy ---------------------------
