@@ -88,15 +88,14 @@ __device__ __forceinline__ void add_planes(uint32_t* planes, uint32_t x) {
 // one ripple for two vectors.
 template <int NPLANES>
 __device__ __forceinline__ void add_planes2(uint32_t* planes, uint32_t a, uint32_t b) {
-  const uint32_t p0 = planes[0];
-  planes[0] = xor3(p0, a, b);
-  uint32_t c = __builtin_amdgcn_bitop3_b32(p0, a, b, 0xE8);  // majority
+  uint32_t c[NPLANES];
+  c[0] = __builtin_amdgcn_bitop3_b32(planes[0], a, b, 0xE8);  // majority: the carry into plane 1
 #pragma unroll
-  for (int k = 1; k < NPLANES; ++k) {
-    const uint32_t n = planes[k] & c;
-    planes[k] ^= c;
-    c = n;
-  }
+  for (int k = 1; k + 1 < NPLANES; ++k) c[k] = planes[k] & c[k - 1];
+  // in place: each plane keeps its register from visit to visit
+  asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(planes[0]) : "v"(a), "v"(b));
+#pragma unroll
+  for (int k = 1; k < NPLANES; ++k) asm("v_xor_b32 %0, %0, %1" : "+v"(planes[k]) : "v"(c[k - 1]));
 }
 
 // Threshold compares of the 32 replicas of a site word against the first LEV
@@ -180,24 +179,31 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
     const uint32_t dx = o ? w.d_up : w.d_dn;
     const int bit_shift = o ? 0 : 1, bit_same = 1 - bit_shift;
     uint32_t ci = w.line0 * w.Lx + 2u * w.m + o;
-    uint32_t* p_own = lds + own;
-    const uint8_t* p_wl = wl + own;
-    const uint32_t* p_nb = lds + own + other;  // same-column neighbour word
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    typedef __attribute__((address_space(3))) const uint8_t lds_u8;
+    // LDS byte addresses of the own word, its weight byte and the
+    // same-column neighbour word, advanced by one pass per visit
+    uint32_t a_own = (uint32_t)(uintptr_t)(lds_u32*)(lds + own);
+    uint32_t a_wl = (uint32_t)(uintptr_t)(lds_u8*)(wl + own);
+    uint32_t a_nb = (uint32_t)(uintptr_t)(lds_u32*)(lds + own + other);
     const uint32_t n_lines = (w.Ly - 1u - w.y0) / w.lp + 1u;  // this thread's lines (y0 < Ly)
-    const uint32_t step = w.own_step;
+    const uint32_t step = w.own_step, step4 = 4u * w.own_step;
+    const uint32_t dx4 = 4u * dx;
+    auto rd = [](uint32_t a) { return *(const lds_u32*)(uintptr_t)a; };
     auto visit = [&](uint32_t dyp, uint32_t dym) {
-      const uint32_t s = *p_own;
-      const uint32_t wp = *p_wl;
+      asm volatile("" : "+v"(a_own), "+v"(a_wl), "+v"(a_nb));
+      const uint32_t s = rd(a_own);
+      const uint32_t wp = *(lds_u8*)(uintptr_t)a_wl;
       uint32_t x[4];
-      x[0] = xor3(s, p_nb[dx], (uint32_t)__builtin_amdgcn_sbfe((int)wp, bit_shift, 1));
-      x[1] = xor3(s, p_nb[0], (uint32_t)__builtin_amdgcn_sbfe((int)wp, bit_same, 1));
-      x[2] = xor3(s, p_nb[dyp], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 2, 1));
-      x[3] = xor3(s, p_nb[dym], (uint32_t)__builtin_amdgcn_sbfe((int)wp, 3, 1));
+      x[0] = xor3(s, rd(a_nb + dx4), (uint32_t)__builtin_amdgcn_sbfe((int)wp, bit_shift, 1));
+      x[1] = xor3(s, rd(a_nb), (uint32_t)__builtin_amdgcn_sbfe((int)wp, bit_same, 1));
+      x[2] = xor3(s, rd(a_nb + 4u * dyp), (uint32_t)__builtin_amdgcn_sbfe((int)wp, 2, 1));
+      x[3] = xor3(s, rd(a_nb + 4u * dym), (uint32_t)__builtin_amdgcn_sbfe((int)wp, 3, 1));
       const uint32_t F = bp_decide<NDIM, LEV, STATS>(x, seed, ci, t, quad0, T1, T2, T3, valid_lanes, n_blocks, n_draws);
-      *p_own = s ^ F;
-      p_own += step;
-      p_wl += step;
-      p_nb += step;
+      *(lds_u32*)(uintptr_t)a_own = s ^ F;
+      a_own += step4;
+      a_wl += step;
+      a_nb += step4;
       ci += w.ci_step;
       return F;
     };
