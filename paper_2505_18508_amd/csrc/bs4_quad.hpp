@@ -88,24 +88,26 @@ struct Bs4Walk {
   uint32_t ci0, ci_step;   // canonical index of (first line of word line gl0, x = 2m), per pass
   uint32_t ci_m;           // 2m
   uint32_t GL, gl0, lp;
+  // 2-D with Ly = 0 mod 4: word lines visited per half-sweep and the +-y
+  // offsets of the first and last visits (only those can wrap)
+  uint32_t nv, dyp_first, dym_first, dyp_last;
 };
 
-// Unsatisfied bonds of the 16 lanes of colour-P word at record `base`,
-// counted bit-sliced: u = u0 + 2 u1 + 4 u2.
-template <int NDIM, int P, bool PART = false>
-__device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const Bs4Walk& wk, uint32_t Y, uint32_t z,
-                                          uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+// Unsatisfied bonds of the 16 lanes of a colour-P word, counted bit-sliced:
+// u = u0 + 2 u1 + 4 u2.  rd(off) reads the word at byte offset off (modulo
+// 2^32) from the word's record; the +y and -y neighbour records are at dyp
+// and dym, Y and z are the word line's coordinates.
+template <int NDIM, int P, bool PART, class Rd>
+__device__ __forceinline__ void bs4_bonds_rd(Rd rd, const Bs4Walk& wk, uint32_t dyp, uint32_t dym, uint32_t Y,
+                                             uint32_t z, uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
   constexpr int DEG = 2 * NDIM;
-  constexpr int O = 1 - P;
-  const uint32_t* rec = (const uint32_t*)(lds + base);
-  own = rec[P];
-  const uint32_t xs = rec[O];
-  const uint32_t xu = ((const uint32_t*)(lds + base + wk.du))[O];
-  const uint32_t xd = ((const uint32_t*)(lds + base + wk.dd))[O];
-  const uint32_t yp = (Y + 1u == wk.LY4) ? base + wk.row - wk.plane : base + wk.row;
-  const uint32_t ym = (Y == 0u) ? base + wk.plane - wk.row : base - wk.row;
-  const uint32_t yn = ((const uint32_t*)(lds + yp))[O];
-  const uint32_t yv = ((const uint32_t*)(lds + ym))[O];
+  constexpr uint32_t O4 = 4u * (1u - (uint32_t)P);
+  own = rd(4u * (uint32_t)P);
+  const uint32_t xs = rd(O4);
+  const uint32_t xu = rd(wk.du + O4);
+  const uint32_t xd = rd(wk.dd + O4);
+  const uint32_t yn = rd(dyp + O4);
+  const uint32_t yv = rd(dym + O4);
   const uint32_t q = ((uint32_t)P + z) & 1u;      // o of the word's first site
   const uint32_t sel = q ? 0x0F0Fu : 0xF0F0u;     // nibbles whose x-shift neighbour is at m + 1
   uint32_t nb[DEG];
@@ -121,15 +123,24 @@ __device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const 
   }
   if (NDIM == 3) {
     const uint32_t vol = wk.plane * wk.Lz;
-    const uint32_t zp = (z + 1u == wk.Lz) ? base + wk.plane - vol : base + wk.plane;
-    const uint32_t zm = (z == 0u) ? base + vol - wk.plane : base - wk.plane;
-    nb[DEG - 2] = ((const uint32_t*)(lds + zp))[O];
-    nb[DEG - 1] = ((const uint32_t*)(lds + zm))[O];
+    nb[DEG - 2] = rd(((z + 1u == wk.Lz) ? wk.plane - vol : wk.plane) + O4);
+    nb[DEG - 1] = rd(((z == 0u) ? vol - wk.plane : 0u - wk.plane) + O4);
   }
   uint32_t x[DEG];
 #pragma unroll
-  for (int d = 0; d < DEG; ++d) x[d] = xor3(own, nb[d], rec[2 + P * DEG + d]);
+  for (int d = 0; d < DEG; ++d) x[d] = xor3(own, nb[d], rd(4u * (2u + (uint32_t)(P * DEG + d))));
   bond_count3<DEG>(x, u0, u1, u2);
+}
+
+// The same for the word at record `base` of lds, its y neighbours found
+// from its word line Y (wrapping at the plane's ends).
+template <int NDIM, int P, bool PART = false>
+__device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const Bs4Walk& wk, uint32_t Y, uint32_t z,
+                                          uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+  const uint32_t dyp = (Y + 1u == wk.LY4) ? wk.row - wk.plane : wk.row;
+  const uint32_t dym = (Y == 0u) ? wk.plane - wk.row : 0u - wk.row;
+  auto rd = [&](uint32_t off) { return *(const uint32_t*)(lds + (uint32_t)(base + off)); };
+  bs4_bonds_rd<NDIM, P, PART>(rd, wk, dyp, dym, Y, z, own, u0, u1, u2);
 }
 
 // Thresholds of the quad's four replicas for one sweep: T[k-1][b] for
@@ -187,6 +198,45 @@ __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t 
   }
 }
 
+// Flip mask of a word from its bond counts: dE = 2 deg - 4u, flip when
+// u >= deg/2, else k = deg/2 - u and the replica flips iff its draw is below
+// T_k.  rows masks the lanes of real sites, q is o of the word's first site.
+template <int NDIM, int LEV, bool STATS, bool PT>
+__device__ __forceinline__ uint32_t bs4_decide(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t rows, uint32_t q,
+                                               uint32_t ci0, uint32_t Lx, const Bs4Args& a, int t, uint32_t quad,
+                                               const QuadThr& th, uint32_t T1, uint32_t T2, uint32_t T3,
+                                               uint32_t valid16, uint32_t& n_blocks, uint32_t& n_draws) {
+  uint32_t acc, k1, k2, k3 = 0u;
+  if (NDIM == 2) {
+    acc = u1 | u2;
+    k1 = u0 & ~acc;
+    k2 = ~(u0 | acc);
+  } else {
+    acc = u2 | (u1 & u0);
+    k1 = u1 & ~u0 & ~u2;
+    k2 = u0 & ~u1 & ~u2;
+    k3 = ~(u0 | u1 | u2);
+  }
+  uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
+  if (LEV > 0) {
+    bs4_draws<(LEV > 0 ? LEV : 1), PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
+    if (STATS) {  // schedule only: per-replica thresholds reject statistics
+      const uint32_t need = (k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u)) & valid16 & rows;
+      n_blocks += 4u;
+      n_draws += __popc(need);
+    }
+  }
+  return (acc | (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u)) & rows;
+}
+
+template <bool FLIPS>
+__device__ __forceinline__ void bs4_count_flips(uint32_t* fl, uint32_t F) {
+  if (FLIPS) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) fl[b] += __popc(F & (0x1111u << b));
+  }
+}
+
 // One half-sweep of colour P over this thread's words, with the first LEV
 // threshold levels nonzero (0: no draws at all).  The word is written back
 // unconditionally: no thread reads a colour-P word during this half-sweep.
@@ -196,6 +246,34 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
                                          uint32_t valid16, uint32_t* fl, uint32_t& n_blocks,
                                          uint32_t& n_draws) {
   const uint32_t Lx = (uint32_t)a.lat.Lx;
+  if (NDIM == 2 && !PART) {
+    // one plane of whole word lines: fixed +-y offsets except on the first
+    // and last visits, and the record's LDS byte address kept in a register
+    // of its own from visit to visit
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    uint32_t r = (uint32_t)(uintptr_t)(lds_u32*)(lds + wk.base0);
+    uint32_t ci0 = wk.ci0;
+    auto visit = [&](uint32_t dyp, uint32_t dym) {
+      asm("" : "+v"(r));
+      auto rd = [&](uint32_t off) { return *(const lds_u32*)(uintptr_t)(r + off); };
+      uint32_t s, u0, u1, u2;
+      bs4_bonds_rd<NDIM, P, false>(rd, wk, dyp, dym, 0u, 0u, s, u0, u1, u2);
+      const uint32_t F = bs4_decide<NDIM, LEV, STATS, PT>(u0, u1, u2, 0xFFFFu, (uint32_t)P, ci0, Lx, a, t, quad, th,
+                                                          T1, T2, T3, valid16, n_blocks, n_draws);
+      *(lds_u32*)(uintptr_t)(r + 4u * (uint32_t)P) = s ^ F;
+      bs4_count_flips<FLIPS>(fl, F);
+      r += wk.step;
+      ci0 += wk.ci_step;
+    };
+    if (wk.nv == 0u) return;
+    const uint32_t r_last = r + (wk.nv - 1u) * wk.step;  // record of the last visit
+    visit(wk.dyp_first, wk.dym_first);
+    if (wk.nv >= 2u) {
+      while (r != r_last) visit(wk.row, 0u - wk.row);
+      visit(wk.dyp_last, 0u - wk.row);
+    }
+    return;
+  }
   uint32_t base = wk.base0, ci0 = wk.ci0;
   uint32_t Y = wk.Y0, z = wk.z0;
   for (uint32_t gl = wk.gl0; gl < wk.GL; gl += wk.lp) {
@@ -206,34 +284,10 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
     uint32_t s, u0, u1, u2;
     bs4_bonds<NDIM, P, PART>(lds, base, wk, Y, z, s, u0, u1, u2);
     const uint32_t rows = (PART && Y + 1u == wk.LY4) ? 0x00FFu : 0xFFFFu;  // lanes of real sites
-    // dE = 2 deg - 4u: flip when u >= deg/2; else k = deg/2 - u
-    uint32_t acc, k1, k2, k3 = 0u;
-    if (NDIM == 2) {
-      acc = u1 | u2;
-      k1 = u0 & ~acc;
-      k2 = ~(u0 | acc);
-    } else {
-      acc = u2 | (u1 & u0);
-      k1 = u1 & ~u0 & ~u2;
-      k2 = u0 & ~u1 & ~u2;
-      k3 = ~(u0 | u1 | u2);
-    }
-    uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-    if (LEV > 0) {
-      const uint32_t q = ((uint32_t)P + z) & 1u;
-      bs4_draws<(LEV > 0 ? LEV : 1), PT>(a.seed, ci0, Lx, q, (uint32_t)t, quad, th, T1, T2, T3, c1, c2, c3);
-      if (STATS) {  // schedule only: per-replica thresholds reject statistics
-        const uint32_t need = (k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u)) & valid16 & rows;
-        n_blocks += 4u;
-        n_draws += __popc(need);
-      }
-    }
-    const uint32_t F = (acc | (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u)) & rows;
+    const uint32_t F = bs4_decide<NDIM, LEV, STATS, PT>(u0, u1, u2, rows, ((uint32_t)P + z) & 1u, ci0, Lx, a, t, quad,
+                                                        th, T1, T2, T3, valid16, n_blocks, n_draws);
     ((uint32_t*)(lds + base))[P] = s ^ F;
-    if (FLIPS) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) fl[b] += __popc(F & (0x1111u << b));
-    }
+    bs4_count_flips<FLIPS>(fl, F);
     base += wk.step;
     if (NDIM == 3) {
       Y += wk.lp_y;
@@ -393,6 +447,13 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   wk.GL = GL;
   wk.gl0 = gl0;
   wk.lp = lp;
+  wk.nv = gl0 < GL ? (GL - 1u - gl0) / lp + 1u : 0u;
+  {
+    const uint32_t gl_last = gl0 + (wk.nv > 0u ? wk.nv - 1u : 0u) * lp;  // 2-D: word line = Y
+    wk.dyp_last = (gl_last + 1u == LY4) ? wk.row - wk.plane : wk.row;
+    wk.dym_first = (gl0 == 0u) ? wk.plane - wk.row : 0u - wk.row;
+    wk.dyp_first = (wk.nv == 1u) ? wk.dyp_last : wk.row;
+  }
   const bool active = tid < (int)(hx * lp);
   const uint32_t valid16 = 0x1111u * ((1u << nvalid) - 1u);
   char* lb = (char*)lds;
