@@ -320,15 +320,23 @@ def test_replica_offset_selects_streams(dev, layout):
     assert (part[0] == full[0][12:52]).all()
 
 
+@pytest.mark.parametrize("rows", [50, 48])
 @pytest.mark.parametrize("bt", [1, 100, 300, 512, 1000])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_block_size_does_not_change_results(dev, bt, layout):
+def test_block_size_does_not_change_results(dev, bt, layout, rows):
+    """Every block size walks a thread's lines differently (one word line per
+    pass up to whole blocks; bp32 pairs of middle lines with an odd one left
+    over; bs4 on 48 rows takes the 2-D walk with per-thread wrap offsets, on
+    50 the general one): results equal the i8 layout's."""
     c = inputs.TORUS_50x100_R16
-    dims = c["dims"]
+    dims = [rows, c["dims"][1]]
     ref = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", layout="i8")
     got = run_gpu(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear", block_threads=bt, layout=layout)
     for x, y in zip(ref, got):
         assert (x == y).all()
+    if rows == 48 and bt == 1000:
+        orc = run_oracle(dims, c["weight_seed"], c["seed"], 36, 200, schedule="linear")
+        assert_same(got, orc)
 
 
 @pytest.mark.parametrize("dims", [[48, 100], [80, 80]])
