@@ -192,13 +192,25 @@ def with_parity(cpu, cpu_spins, final):
     return cpu
 
 
-def ttt_leg(log=None):
+def ttt_workload(seeds=None):
+    """The time-to-target workload, with other run seeds if given."""
+    if seeds is None:
+        return TTT
+    seeds = tuple(int(x) for x in seeds)
+    if not seeds:
+        raise ValueError("the time-to-target leg needs at least one run seed")
+    return dict(TTT, seeds=seeds,
+                name=TTT["name"].rsplit(", run seeds", 1)[0] + ", run seeds " + ", ".join(str(x) for x in seeds))
+
+
+def ttt_leg(log=None, seeds=None):
     """Median time to 99.9 % of the instance's best cut for the plain,
     learned-cull and energy-cull forms (eq. (3)-(5), t_trial = batch time / R)
-    on the TTT workload; every step runs in the library's kernels."""
+    on the TTT workload (run seeds: the workload's, or `seeds`); every step
+    runs in the library's kernels."""
     from paper_2505_18508_amd import create_graph, learn, metrics
 
-    W = TTT
+    W = ttt_workload(seeds)
     g = create_graph(W["dims"], W["weight_seed"])
     model = learn.Model.load(os.path.join(ROOT, W["model"]))
     runs = {m: [] for m in learn.METHODS}
@@ -316,6 +328,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-target leg")
+    ap.add_argument("--ttt-only", action="store_true",
+                    help="run only the time-to-target leg and print its JSON object")
+    ap.add_argument("--ttt-seeds", default=None, help="run seeds of the time-to-target leg, comma-separated")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default=DEFAULT_WORKLOAD)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a reference kernel of known traffic for counters)")
@@ -326,6 +341,11 @@ def main():
         print("bench.py measures one GPU only: the replica-parallel path has no cross-GPU step to time "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    ttt_seeds = [int(x) for x in args.ttt_seeds.split(",")] if args.ttt_seeds else None
+    if args.ttt_only:
+        print(json.dumps(ttt_leg(log=lambda m: print(m, file=sys.stderr, flush=True), seeds=ttt_seeds)))
+        return
 
     cpu = cpu_spins = None
     if not args.no_cpu:
@@ -440,7 +460,7 @@ def main():
     g.close()
     if not args.no_ttt and args.workload == DEFAULT_WORKLOAD:
         del spins, cut, energy, flips
-        out["ttt"] = ttt_leg(log=lambda m: print(m, file=sys.stderr, flush=True))
+        out["ttt"] = ttt_leg(log=lambda m: print(m, file=sys.stderr, flush=True), seeds=ttt_seeds)
     print(json.dumps(out))
 
 

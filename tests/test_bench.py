@@ -116,3 +116,15 @@ def test_ttt_leg_configuration_and_model():
     assert len(learn.checkpoints(W["S"], W["window"])) == 19
     assert W["dims"] == bench.WORKLOADS[bench.DEFAULT_WORKLOAD]["dims"]
     assert W["weight_seed"] == bench.WORKLOADS[bench.DEFAULT_WORKLOAD]["weight_seed"]
+
+
+def test_ttt_workload_seeds():
+    """--ttt-seeds swaps the run seeds and the workload's name, nothing else."""
+    W = bench.ttt_workload([201, 202, 203, 204, 205])
+    assert W["seeds"] == (201, 202, 203, 204, 205)
+    assert W["name"].endswith("run seeds 201, 202, 203, 204, 205")
+    assert {k: v for k, v in W.items() if k not in ("seeds", "name")} == \
+        {k: v for k, v in bench.TTT.items() if k not in ("seeds", "name")}
+    assert bench.ttt_workload() is bench.TTT
+    with pytest.raises(ValueError):
+        bench.ttt_workload([])
