@@ -88,18 +88,23 @@ struct Bs4Walk {
   uint32_t ci0, ci_step;   // canonical index of (first line of word line gl0, x = 2m), per pass
   uint32_t ci_m;           // 2m
   uint32_t GL, gl0, lp;
-  // 2-D with Ly = 0 mod 4: word lines visited per half-sweep and the +-y
-  // offsets of the first and last visits (only those can wrap)
+  // 2-D: word lines visited per half-sweep and, for the first and last
+  // visits (only those can wrap), the +-y offsets, the shifts that bring the
+  // +y / -y neighbour rows in (12, or 4 across the wrap of a plane whose last
+  // word line holds two rows) and the lanes of real sites
   uint32_t nv, dyp_first, dym_first, dyp_last;
+  uint32_t shp_first, shm_first, shp_last, rows_first, rows_last;
 };
 
 // Unsatisfied bonds of the 16 lanes of a colour-P word, counted bit-sliced:
 // u = u0 + 2 u1 + 4 u2.  rd(off) reads the word at byte offset off (modulo
 // 2^32) from the word's record; the +y and -y neighbour records are at dyp
-// and dym, Y and z are the word line's coordinates.
+// and dym, their rows come in shifted by shp and shm nibble bits (PART; else
+// 12), z is the word line's plane.
 template <int NDIM, int P, bool PART, class Rd>
-__device__ __forceinline__ void bs4_bonds_rd(Rd rd, const Bs4Walk& wk, uint32_t dyp, uint32_t dym, uint32_t Y,
-                                             uint32_t z, uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
+__device__ __forceinline__ void bs4_bonds_rd(Rd rd, const Bs4Walk& wk, uint32_t dyp, uint32_t dym, uint32_t shp,
+                                             uint32_t shm, uint32_t z, uint32_t& own, uint32_t& u0, uint32_t& u1,
+                                             uint32_t& u2) {
   constexpr int DEG = 2 * NDIM;
   constexpr uint32_t O4 = 4u * (1u - (uint32_t)P);
   own = rd(4u * (uint32_t)P);
@@ -115,8 +120,8 @@ __device__ __forceinline__ void bs4_bonds_rd(Rd rd, const Bs4Walk& wk, uint32_t 
   nb[1] = (xu & sel) | (xd & ~sel);
   if (PART) {
     // row Ly - 1 is nibble 1 of the last word line, so the wrap shifts by one nibble
-    nb[2] = (xs >> 4) | (yn << (Y + 1u == wk.LY4 ? 4u : 12u));
-    nb[3] = (xs << 4) | (yv >> (Y == 0u ? 4u : 12u));
+    nb[2] = (xs >> 4) | (yn << shp);
+    nb[3] = (xs << 4) | (yv >> shm);
   } else {
     nb[2] = (xs >> 4) | (yn << 12);
     nb[3] = (xs << 4) | (yv >> 12);
@@ -139,8 +144,10 @@ __device__ __forceinline__ void bs4_bonds(const char* lds, uint32_t base, const 
                                           uint32_t& own, uint32_t& u0, uint32_t& u1, uint32_t& u2) {
   const uint32_t dyp = (Y + 1u == wk.LY4) ? wk.row - wk.plane : wk.row;
   const uint32_t dym = (Y == 0u) ? wk.plane - wk.row : 0u - wk.row;
+  const uint32_t shp = (PART && Y + 1u == wk.LY4) ? 4u : 12u;
+  const uint32_t shm = (PART && Y == 0u) ? 4u : 12u;
   auto rd = [&](uint32_t off) { return *(const uint32_t*)(lds + (uint32_t)(base + off)); };
-  bs4_bonds_rd<NDIM, P, PART>(rd, wk, dyp, dym, Y, z, own, u0, u1, u2);
+  bs4_bonds_rd<NDIM, P, PART>(rd, wk, dyp, dym, shp, shm, z, own, u0, u1, u2);
 }
 
 // Thresholds of the quad's four replicas for one sweep: T[k-1][b] for
@@ -246,19 +253,19 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
                                          uint32_t valid16, uint32_t* fl, uint32_t& n_blocks,
                                          uint32_t& n_draws) {
   const uint32_t Lx = (uint32_t)a.lat.Lx;
-  if (NDIM == 2 && !PART) {
-    // one plane of whole word lines: fixed +-y offsets except on the first
-    // and last visits, and the record's LDS byte address kept in a register
-    // of its own from visit to visit
+  if (NDIM == 2) {
+    // one plane: fixed +-y offsets and shifts on every visit but the first
+    // and the last, and the record's LDS byte address kept in a register of
+    // its own from visit to visit
     typedef __attribute__((address_space(3))) uint32_t lds_u32;
     uint32_t r = (uint32_t)(uintptr_t)(lds_u32*)(lds + wk.base0);
     uint32_t ci0 = wk.ci0;
-    auto visit = [&](uint32_t dyp, uint32_t dym) {
+    auto visit = [&](uint32_t dyp, uint32_t dym, uint32_t shp, uint32_t shm, uint32_t rows) {
       asm("" : "+v"(r));
       auto rd = [&](uint32_t off) { return *(const lds_u32*)(uintptr_t)(r + off); };
       uint32_t s, u0, u1, u2;
-      bs4_bonds_rd<NDIM, P, false>(rd, wk, dyp, dym, 0u, 0u, s, u0, u1, u2);
-      const uint32_t F = bs4_decide<NDIM, LEV, STATS, PT>(u0, u1, u2, 0xFFFFu, (uint32_t)P, ci0, Lx, a, t, quad, th,
+      bs4_bonds_rd<NDIM, P, PART>(rd, wk, dyp, dym, shp, shm, 0u, s, u0, u1, u2);
+      const uint32_t F = bs4_decide<NDIM, LEV, STATS, PT>(u0, u1, u2, rows, (uint32_t)P, ci0, Lx, a, t, quad, th,
                                                           T1, T2, T3, valid16, n_blocks, n_draws);
       *(lds_u32*)(uintptr_t)(r + 4u * (uint32_t)P) = s ^ F;
       bs4_count_flips<FLIPS>(fl, F);
@@ -267,10 +274,10 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
     };
     if (wk.nv == 0u) return;
     const uint32_t r_last = r + (wk.nv - 1u) * wk.step;  // record of the last visit
-    visit(wk.dyp_first, wk.dym_first);
+    visit(wk.dyp_first, wk.dym_first, wk.shp_first, wk.shm_first, wk.rows_first);
     if (wk.nv >= 2u) {
-      while (r != r_last) visit(wk.row, 0u - wk.row);
-      visit(wk.dyp_last, 0u - wk.row);
+      while (r != r_last) visit(wk.row, 0u - wk.row, 12u, 12u, 0xFFFFu);
+      visit(wk.dyp_last, 0u - wk.row, wk.shp_last, 12u, wk.rows_last);
     }
     return;
   }
@@ -450,9 +457,15 @@ __device__ __forceinline__ void bs4_quad(const Bs4Args& a, const int r0, uint32_
   wk.nv = gl0 < GL ? (GL - 1u - gl0) / lp + 1u : 0u;
   {
     const uint32_t gl_last = gl0 + (wk.nv > 0u ? wk.nv - 1u : 0u) * lp;  // 2-D: word line = Y
-    wk.dyp_last = (gl_last + 1u == LY4) ? wk.row - wk.plane : wk.row;
-    wk.dym_first = (gl0 == 0u) ? wk.plane - wk.row : 0u - wk.row;
+    const bool wrap_p = gl_last + 1u == LY4, wrap_m = gl0 == 0u;
+    wk.dyp_last = wrap_p ? wk.row - wk.plane : wk.row;
+    wk.shp_last = (PART && wrap_p) ? 4u : 12u;
+    wk.rows_last = (PART && wrap_p) ? 0x00FFu : 0xFFFFu;
+    wk.dym_first = wrap_m ? wk.plane - wk.row : 0u - wk.row;
+    wk.shm_first = (PART && wrap_m) ? 4u : 12u;
     wk.dyp_first = (wk.nv == 1u) ? wk.dyp_last : wk.row;
+    wk.shp_first = (wk.nv == 1u) ? wk.shp_last : 12u;
+    wk.rows_first = (wk.nv == 1u) ? wk.rows_last : 0xFFFFu;
   }
   const bool active = tid < (int)(hx * lp);
   const uint32_t valid16 = 0x1111u * ((1u << nvalid) - 1u);
