@@ -98,6 +98,24 @@ __device__ __forceinline__ void add_planes2(uint32_t* planes, uint32_t a, uint32
   for (int k = 1; k < NPLANES; ++k) asm("v_xor_b32 %0, %0, %1" : "+v"(planes[k]) : "v"(c[k - 1]));
 }
 
+// Add four bit vectors at once: two full adders into the lowest plane (their
+// carries have weight 2), a third adding both carries into the next plane,
+// then its carry rippled upwards -- one ripple for four vectors.
+template <int NPLANES>
+__device__ __forceinline__ void add_planes4(uint32_t* planes, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  const uint32_t c1 = __builtin_amdgcn_bitop3_b32(planes[0], a, b, 0xE8);  // majority
+  asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(planes[0]) : "v"(a), "v"(b));
+  const uint32_t c2 = __builtin_amdgcn_bitop3_b32(planes[0], c, d, 0xE8);
+  asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(planes[0]) : "v"(c), "v"(d));
+  uint32_t e[NPLANES];
+  e[1] = __builtin_amdgcn_bitop3_b32(planes[1], c1, c2, 0xE8);  // carry into plane 2
+#pragma unroll
+  for (int k = 2; k + 1 < NPLANES; ++k) e[k] = planes[k] & e[k - 1];
+  asm("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(planes[1]) : "v"(c1), "v"(c2));
+#pragma unroll
+  for (int k = 2; k < NPLANES; ++k) asm("v_xor_b32 %0, %0, %1" : "+v"(planes[k]) : "v"(e[k - 1]));
+}
+
 // Threshold compares of the 32 replicas of a site word against the first LEV
 // thresholds; bit j of c[k] = (Philox word of replica j) < T_{k+1}.
 template <int LEV>
@@ -213,9 +231,17 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
       if (FLIPS) add_planes<8>(fplanes, F_first);
       return;
     }
-    // middle lines two at a time, their flips added as a pair
+    // middle lines four at a time, their flips added together; then a pair
+    // and a single line for what is left
     const uint32_t n_mid = n_lines - 2u;
-    for (uint32_t k = 0u; k < n_mid / 2u; ++k) {
+    for (uint32_t k = 0u; k < n_mid / 4u; ++k) {
+      const uint32_t Fa = visit(w.row, 0u - w.row);
+      const uint32_t Fb = visit(w.row, 0u - w.row);
+      const uint32_t Fc = visit(w.row, 0u - w.row);
+      const uint32_t Fd = visit(w.row, 0u - w.row);
+      if (FLIPS) add_planes4<8>(fplanes, Fa, Fb, Fc, Fd);
+    }
+    if (n_mid & 2u) {
       const uint32_t Fa = visit(w.row, 0u - w.row);
       const uint32_t Fb = visit(w.row, 0u - w.row);
       if (FLIPS) add_planes2<8>(fplanes, Fa, Fb);
