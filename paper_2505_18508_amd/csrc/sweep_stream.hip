@@ -31,6 +31,8 @@ struct StreamArgs {
   unsigned long long* spart;  // [groups][blocks_x][2] block-owned RNG counts (STATS)
   uint64_t seed;
   int32_t n_replicas, replica_offset, groups;
+  FastDiv div_hx;  // division by the words per line of one colour
+  FastDiv div_bx;  // division by the blocks per replica group (gridDim.x)
 };
 
 // One stage of a 32 x 32 bit transpose across the 32 lanes of a half-wave
@@ -82,7 +84,7 @@ __device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, i
   const uint32_t lines = (uint32_t)L.lines, half = (uint32_t)L.half;
   const uint32_t plane = hx * Ly;
   const uint32_t l0 = strip * (uint32_t)K;
-  const uint32_t z = NDIM == 2 ? 0u : l0 / Ly;
+  const uint32_t z = NDIM == 2 ? 0u : fdiv(l0, L.div_ly);
   uint32_t y = l0 - z * Ly;
   const uint32_t m_up = (m + 1u == hx) ? 0u : m + 1u;
   const uint32_t m_dn = (m == 0u) ? hx - 1u : m - 1u;
@@ -109,6 +111,9 @@ __device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, i
     }
   };
   uint32_t cur[6], nxt[6];
+  uint32_t Fk[K];  // accepted flips of each line of the strip (0 past the lattice's last line)
+#pragma unroll
+  for (int k = 0; k < K; ++k) Fk[k] = 0u;
   load_line(own, oth, y, omask, cur);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -155,13 +160,7 @@ __device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, i
       }
     }
     w[own] = s ^ F;
-    uint32_t c = F;  // add F into the bit-sliced counters
-#pragma unroll
-    for (int b = 0; b < NP; ++b) {
-      const uint32_t carry = fp[b] & c;
-      fp[b] ^= c;
-      c = carry;
-    }
+    Fk[k] = F;
     ym = x0;
     x0 = yp;
     own += hx;
@@ -171,6 +170,27 @@ __device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, i
     ci += Lx + ((omask & 2u) - 1u);  // next line, x parity flipped: +Lx +1 if o becomes 1, +Lx -1 if 0
 #pragma unroll
     for (int e = 0; e < 6; ++e) cur[e] = nxt[e];
+  }
+  // the strip's flips per replica, bit-sliced (fp starts at zero: one strip
+  // per thread and launch)
+  if constexpr (K == 1) {
+    fp[0] = Fk[0];
+  } else if constexpr (K == 2) {
+    fp[0] = Fk[0] ^ Fk[1];
+    fp[1] = Fk[0] & Fk[1];
+  } else if constexpr (K == 4) {
+    bond_count3<4>(Fk, fp[0], fp[1], fp[2]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      uint32_t c = Fk[k];
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
+        const uint32_t carry = fp[b] & c;
+        fp[b] ^= c;
+        c = carry;
+      }
+    }
   }
 }
 
@@ -187,7 +207,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
   const uint32_t lin = blockIdx.x + blockIdx.y * gridDim.x;
   const uint32_t per = nblk / 8u, rem = nblk % 8u, xcd = lin % 8u;
   const uint32_t logical = xcd * per + (xcd < rem ? xcd : rem) + lin / 8u;
-  const int g = (int)(logical / gridDim.x);
+  const int g = (int)fdiv(logical, a.div_bx);
   const uint32_t bx = logical - (uint32_t)g * gridDim.x;
   const uint32_t hx = (uint32_t)L.hx;
   const uint32_t n_items = hx * (((uint32_t)L.lines + (uint32_t)K - 1u) / (uint32_t)K);
@@ -203,7 +223,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
   for (int b = 0; b < NP; ++b) fp[b] = 0u;
   uint32_t n_words = 0u, n_draws = 0u;
   if (item < n_items) {
-    const uint32_t strip = item / hx;
+    const uint32_t strip = fdiv(item, a.div_hx);
     const uint32_t m = item - strip * hx;
     uint32_t* w = a.words + (size_t)g * L.n;
     const uint32_t quad0 = (uint32_t)(a.replica_offset + r0) >> 2;
@@ -438,6 +458,8 @@ hipError_t launch_sweep_stream(const ising_graph* g, const SweepLaunch& s, uint3
   a.n_replicas = s.n_replicas;
   a.replica_offset = s.replica_offset;
   a.groups = groups;
+  a.div_hx = make_fastdiv((uint32_t)L.hx);
+  a.div_bx = make_fastdiv((uint32_t)bx);
   const dim3 grid((unsigned)bx, (unsigned)groups);
   auto go = [&](auto kernel) {
     for (int t = s.t_begin; t < s.t_end; ++t)
