@@ -236,6 +236,8 @@ __device__ __forceinline__ uint32_t bs4_decide(uint32_t u0, uint32_t u1, uint32_
   return (acc | (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u)) & rows;
 }
 
+// Accepted flips of a word added to the four replicas' counters (replica b
+// owns lanes 4 j + b).
 template <bool FLIPS>
 __device__ __forceinline__ void bs4_count_flips(uint32_t* fl, uint32_t F) {
   if (FLIPS) {
@@ -261,7 +263,7 @@ __device__ __forceinline__ void bs4_half(char* lds, const Bs4Walk& wk, const Bs4
     uint32_t r = (uint32_t)(uintptr_t)(lds_u32*)(lds + wk.base0);
     uint32_t ci0 = wk.ci0;
     auto visit = [&](uint32_t dyp, uint32_t dym, uint32_t shp, uint32_t shm, uint32_t rows) {
-      asm("" : "+v"(r));
+      asm("" : "+v"(r));  // opaque: r stays the induction register the reads use
       auto rd = [&](uint32_t off) { return *(const lds_u32*)(uintptr_t)(r + off); };
       uint32_t s, u0, u1, u2;
       bs4_bonds_rd<NDIM, P, PART>(rd, wk, dyp, dym, shp, shm, 0u, s, u0, u1, u2);

@@ -209,6 +209,8 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
     const uint32_t dx4 = 4u * dx;
     auto rd = [](uint32_t a) { return *(const lds_u32*)(uintptr_t)a; };
     auto visit = [&](uint32_t dyp, uint32_t dym) {
+      // opaque to the compiler, so each address is its own induction
+      // register and a read uses it directly (no base added per read)
       asm volatile("" : "+v"(a_own), "+v"(a_wl), "+v"(a_nb));
       const uint32_t s = rd(a_own);
       const uint32_t wp = *(lds_u8*)(uintptr_t)a_wl;
