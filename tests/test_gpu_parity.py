@@ -384,6 +384,35 @@ def test_too_large_torus_is_rejected(dev):
         assert e.value.code == ising.E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("entry", ["run_trials", "run_trials_noalloc"])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_degenerate_windows_and_zero_replicas_are_rejected(dev, layout, entry):
+    """An empty window, one past the schedule's end, one running backwards and
+    a call with no replicas are argument errors that leave the spins as they
+    were; a one-sweep schedule runs (its single beta is beta0)."""
+    import torch
+
+    ising = _ising()
+    run = getattr(ising, entry)
+    dims = [8, 12]
+    g = ising.create_graph(dims, 3)
+    s = torch.ones((8, g.n), dtype=torch.int8, device="cuda")
+    for begin, end in ((5, 5), (0, 11), (6, 4)):
+        with pytest.raises(ising.IsingError) as e:
+            run(g, s, 1, 10, begin, end, layout=layout, init_spins=False)
+        assert e.value.code == ising.E_ARG
+    torch.cuda.synchronize()
+    assert (s == 1).all()
+    empty = torch.zeros((0, g.n), dtype=torch.int8, device="cuda")
+    with pytest.raises(ising.IsingError) as e:
+        run(g, empty, 1, 10, layout=layout)
+    assert e.value.code == ising.E_ARG
+    g.close()
+    gpu = run_gpu(dims, 3, 5, 8, 1, layout=layout)
+    orc = run_oracle(dims, 3, 5, 8, 1)
+    assert_same(gpu, orc)
+
+
 @pytest.mark.parametrize("dims", [[200, 204], [40, 40, 40]])
 def test_bs4_rejects_lattices_too_large_for_lds(dev, dims):
     """A forced bit-sliced packing of a lattice whose records exceed a block's LDS."""
