@@ -108,6 +108,56 @@ __device__ __forceinline__ void lt_shift_in4(uint32_t& c1, uint32_t& c2, uint32_
 #undef ISING_LT3
   }
 }
+// One level of the above as volatile statements, for a chain that runs under
+// a wave-uniform branch: plain asm counts as free of side effects, and the
+// compiler may hoist the whole chain out of the branch.
+template <bool FIRST = false>
+__device__ __forceinline__ void lt_shift_in4_kept(uint32_t& c, const uint32_t* u, uint32_t T) {
+  uint32_t d;
+#define ISING_LT1(S1)                                                                                        \
+  ISING_LT_SUB(2, 6) S1(1) ISING_LT_SUB(3, 7) ISING_LT_ADD(1) ISING_LT_SUB(4, 8) ISING_LT_ADD(1) ISING_LT_SUB(5, 9) \
+  ISING_LT_ADD(1)
+  if (FIRST)
+    asm volatile(ISING_LT1(ISING_LT_SET)
+                 : "=&v"(d), "=&v"(c)
+                 : "s"(T), "s"(T), "s"(T), "s"(T), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+                 : "vcc");
+  else
+    asm volatile(ISING_LT1(ISING_LT_ADD)
+                 : "=&v"(d), "+v"(c)
+                 : "s"(T), "s"(T), "s"(T), "s"(T), "v"(u[3]), "v"(u[2]), "v"(u[1]), "v"(u[0])
+                 : "vcc");
+#undef ISING_LT1
+}
+// Bits (u_31 < T(31), ..., u_0 < T(0)) of 32 words, word j compared with
+// T_hi where bit j of sel is set and with T_lo elsewhere: one chain for two
+// levels.  The result register starts as sel; each add with carry shifts the
+// previous word's borrow in at the bottom and the next word's selector bit
+// out at the top, into the carry that picks the threshold.  Three
+// instructions a word (select, borrow, add) against four for two chains, and
+// the carry never leaves the block.
+#define ISING_SEL_STEP(U)                      \
+  "v_cndmask_b32_e32 %1, %3, %4, vcc\n\t"      \
+  "v_sub_co_u32_e32 %2, vcc, %" #U ", %1\n\t" \
+  "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc\n\t"
+__device__ __forceinline__ uint32_t lt_select32(const uint32_t* u, uint32_t sel, uint32_t T_lo, uint32_t T_hi) {
+  uint32_t c = sel, t, d;
+  asm("v_add_co_u32_e32 %0, vcc, %0, %0\n\t"
+      ISING_SEL_STEP(36) ISING_SEL_STEP(35) ISING_SEL_STEP(34) ISING_SEL_STEP(33) ISING_SEL_STEP(32) ISING_SEL_STEP(31)
+      ISING_SEL_STEP(30) ISING_SEL_STEP(29) ISING_SEL_STEP(28) ISING_SEL_STEP(27) ISING_SEL_STEP(26) ISING_SEL_STEP(25)
+      ISING_SEL_STEP(24) ISING_SEL_STEP(23) ISING_SEL_STEP(22) ISING_SEL_STEP(21) ISING_SEL_STEP(20) ISING_SEL_STEP(19)
+      ISING_SEL_STEP(18) ISING_SEL_STEP(17) ISING_SEL_STEP(16) ISING_SEL_STEP(15) ISING_SEL_STEP(14) ISING_SEL_STEP(13)
+      ISING_SEL_STEP(12) ISING_SEL_STEP(11) ISING_SEL_STEP(10) ISING_SEL_STEP(9) ISING_SEL_STEP(8) ISING_SEL_STEP(7)
+      ISING_SEL_STEP(6) ISING_SEL_STEP(5)
+      : "+v"(c), "=&v"(t), "=&v"(d)
+      : "v"(T_lo), "v"(T_hi), "v"(u[0]), "v"(u[1]), "v"(u[2]), "v"(u[3]), "v"(u[4]), "v"(u[5]), "v"(u[6]),
+        "v"(u[7]), "v"(u[8]), "v"(u[9]), "v"(u[10]), "v"(u[11]), "v"(u[12]), "v"(u[13]), "v"(u[14]), "v"(u[15]),
+        "v"(u[16]), "v"(u[17]), "v"(u[18]), "v"(u[19]), "v"(u[20]), "v"(u[21]), "v"(u[22]), "v"(u[23]),
+        "v"(u[24]), "v"(u[25]), "v"(u[26]), "v"(u[27]), "v"(u[28]), "v"(u[29]), "v"(u[30]), "v"(u[31])
+      : "vcc");
+  return c;
+}
+#undef ISING_SEL_STEP
 #undef ISING_LT_SUB
 #undef ISING_LT_ADD
 #undef ISING_LT_SET
