@@ -26,6 +26,7 @@
 #include "internal.hpp"
 #include "philox.hpp"
 #include "reduce.hpp"
+#include "word32.hpp"
 
 namespace ising {
 namespace {
@@ -116,87 +117,6 @@ __device__ __forceinline__ void add_planes4(uint32_t* planes, uint32_t a, uint32
   for (int k = 2; k < NPLANES; ++k) asm("v_xor_b32 %0, %0, %1" : "+v"(planes[k]) : "v"(e[k - 1]));
 }
 
-// Sweeps whose smallest nonzero threshold lies below this bound run the
-// screened compares (draw_compare): a wave of 64 sites draws 2,048 words per
-// visit, so a level's chain is then skipped in most waves.
-constexpr uint32_t kScreenBelow = 1u << 21;
-
-// The kernel's per-sweep mode: 2 x (number of nonzero thresholds) + 1 when
-// the compares are screened.  A function of the schedule alone, the same for
-// every thread of the block.
-template <int NDIM>
-__device__ __forceinline__ int bp_mode(uint32_t T1, uint32_t T2, uint32_t T3) {
-  const int lev = sweep_levels<NDIM>(T1, T2, T3);
-  const uint32_t low = lev == 1 ? T1 : lev == 2 ? T2 : T3;
-  return 2 * lev + (lev > 0 && low < kScreenBelow ? 1 : 0);
-}
-
-// Bits of the 32 words u (replica j in bit j) below T, where mn is this
-// lane's smallest word: when no lane of the wave holds a word below T every
-// lane's result is zero, and the wave skips the chain.
-__device__ __forceinline__ uint32_t screened_lt(const uint32_t* u, uint32_t mn, uint32_t T) {
-  uint32_t c = 0u;
-  if (__builtin_amdgcn_ballot_w64(mn < T) != 0u) {
-#pragma unroll
-    for (int q = 7; q >= 0; --q) {
-      if (q == 7)
-        lt_shift_in4_kept<true>(c, u + 4 * q, T);
-      else
-        lt_shift_in4_kept(c, u + 4 * q, T);
-    }
-  }
-  return c;
-}
-
-// Threshold compares of the 32 replicas of a site word against the first LEV
-// thresholds; bit j of c[k] = (Philox word of replica j) < T_{k+1}.  SCREEN:
-// the words are kept and each level's chain runs only in waves where some
-// word falls below its threshold (the same bits, fewer instructions where
-// such words are rare).
-template <int LEV, bool SCREEN>
-__device__ __forceinline__ void draw_compare(uint64_t seed, uint32_t ci, uint32_t t, uint32_t quad0, uint32_t T1,
-                                             uint32_t T2, uint32_t T3, uint32_t& c1, uint32_t& c2, uint32_t& c3) {
-  if (!SCREEN) {
-#pragma unroll
-    for (int q = 7; q >= 0; --q) {
-      const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-      if (q == 7)
-        lt_shift_in4<LEV, true>(c1, c2, c3, r.v, T1, T2, T3);
-      else
-        lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
-    }
-    return;
-  }
-  uint32_t u[32];
-  uint32_t mn = 0xFFFFFFFFu;
-#pragma unroll
-  for (int q = 7; q >= 0; --q) {
-    const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) u[4 * q + j] = r.v[j];
-    mn = min(min(mn, r.v[0]), r.v[1]);
-    mn = min(min(mn, r.v[2]), r.v[3]);
-  }
-  // T1 >= T2 >= T3: no word below T1 leaves the lower levels empty as well
-  c1 = screened_lt(u, mn, T1);
-  if (LEV >= 2) c2 = screened_lt(u, mn, T2);
-  if (LEV >= 3) c3 = screened_lt(u, mn, T3);
-}
-
-// Two levels in one chain: bit j = (Philox word of replica j) < T_2 where bit
-// j of k2 is set, < T_1 elsewhere.
-__device__ __forceinline__ uint32_t draw_select2(uint64_t seed, uint32_t ci, uint32_t t, uint32_t quad0, uint32_t T1,
-                                                 uint32_t T2, uint32_t k2) {
-  uint32_t u[32];
-#pragma unroll
-  for (int q = 7; q >= 0; --q) {
-    const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) u[4 * q + j] = r.v[j];
-  }
-  return lt_select32(u, k2, T1, T2);
-}
-
 // Per-thread constants of the walk over a colour's site words: column m of
 // lines line0, line0 + lp, ... (as in the four-replica kernel).
 struct BpWalk {
@@ -205,51 +125,6 @@ struct BpWalk {
   uint32_t d_up, d_dn, row, plane, dyp_wrap, dym_wrap, dzp_wrap, dzm_wrap;
   uint32_t own_step, ci_step;
 };
-
-// Flip decisions of one site word: x[d] = unsatisfied-bond bits of slot d
-// (any slot order: only their count matters), s = the word.  dE = 2 deg - 4u
-// with u the count: flip when u >= deg/2, else k = deg/2 - u and the replica
-// flips iff its Philox word is below T_k.  LEV = number of nonzero thresholds
-// (they decrease with k, so the nonzero ones are a prefix); 0 draws nothing.
-template <int NDIM, int LEV, bool SCREEN, bool STATS>
-__device__ __forceinline__ uint32_t bp_decide(const uint32_t* x, uint64_t seed, uint32_t ci, uint32_t t, uint32_t quad0,
-                                              uint32_t T1, uint32_t T2, uint32_t T3, uint32_t valid_lanes,
-                                              uint32_t& n_blocks, uint32_t& n_draws) {
-  constexpr int DEG = 2 * NDIM;
-  uint32_t u0, u1, u2;
-  bond_count3<DEG>(x, u0, u1, u2);
-  uint32_t acc, k1, k2, k3 = 0u;
-  if (NDIM == 2) {
-    acc = u1 | u2;        // u >= 2
-    k1 = u0 & ~acc;       // u == 1
-    k2 = ~(u0 | acc);     // u == 0
-  } else {
-    acc = u2 | (u1 & u0);           // u >= 3
-    k1 = u1 & ~u0 & ~u2;            // u == 2
-    k2 = u0 & ~u1 & ~u2;            // u == 1
-    k3 = ~(u0 | u1 | u2);           // u == 0
-  }
-  if (LEV == 0) return acc;
-  if (LEV == 2 && !SCREEN) {
-    // every replica that does not flip outright needs a draw: k1 | k2 (2-D),
-    // and with T3 = 0 a 3-D replica at k = 3 never flips
-    const uint32_t c = draw_select2(seed, ci, t, quad0, T1, T2, k2);
-    const uint32_t need = k1 | k2;
-    if (STATS) {
-      n_blocks += 8u;
-      n_draws += __popc(need & valid_lanes);
-    }
-    return acc | (need & c);
-  }
-  uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-  draw_compare<LEV, SCREEN>(seed, ci, t, quad0, T1, T2, T3, c1, c2, c3);
-  if (STATS) {
-    const uint32_t need = k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u);
-    n_blocks += 8u;
-    n_draws += __popc(need & valid_lanes);
-  }
-  return acc | (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u);
-}
 
 // One colour half-sweep of this thread's site words.  EVEN2D: a 2-D torus
 // walked with an even number of lines per pass, so every line of the thread
@@ -260,7 +135,7 @@ template <int NDIM, int LEV, bool SCREEN, bool FLIPS, bool STATS, bool EVEN2D>
 __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, const BpWalk& w, uint32_t p,
                                               uint64_t seed, uint32_t t, uint32_t quad0, uint32_t T1, uint32_t T2,
                                               uint32_t T3, uint32_t valid_lanes, uint32_t* fplanes,
-                                              uint32_t& n_blocks, uint32_t& n_draws) {
+                                              uint32_t& n_words, uint32_t& n_draws) {
   constexpr int DEG = 2 * NDIM;
   const uint32_t other = (1u - 2u * p) * w.half;
   uint32_t own = p * w.half + w.line0 * w.hx + w.m;
@@ -297,7 +172,7 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
       x[2] = xor3(s, rd(a_nb + 4u * dyp), (uint32_t)__builtin_amdgcn_sbfe((int)wp, 2, 1));
       x[3] = xor3(s, rd(a_nb + 4u * dym), (uint32_t)__builtin_amdgcn_sbfe((int)wp, 3, 1));
       const uint32_t F =
-          bp_decide<NDIM, LEV, SCREEN, STATS>(x, seed, ci, t, quad0, T1, T2, T3, valid_lanes, n_blocks, n_draws);
+          w32_decide<NDIM, LEV, SCREEN, STATS>(x, seed, ci, t, quad0, T1, T2, T3, valid_lanes, n_words, n_draws);
       *(lds_u32*)(uintptr_t)a_own = s ^ F;
       a_own += step4;
       a_wl += step;
@@ -358,8 +233,8 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
       const uint32_t plus = (uint32_t)__builtin_amdgcn_sbfe((int)wp, d, 1);  // all ones iff w = +1
       x[d] = xor3(s, lds[nb[d]], plus);
     }
-    const uint32_t F = bp_decide<NDIM, LEV, SCREEN, STATS>(x, seed, ci0 + o, t, quad0, T1, T2, T3, valid_lanes, n_blocks,
-                                                   n_draws);
+    const uint32_t F =
+        w32_decide<NDIM, LEV, SCREEN, STATS>(x, seed, ci0 + o, t, quad0, T1, T2, T3, valid_lanes, n_words, n_draws);
     lds[own] = s ^ F;
     if (FLIPS) add_planes<8>(fplanes, F);
     own += w.own_step;
@@ -373,7 +248,7 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
   }
 }
 
-// Sweeps t, t + 1, ... of the window while their mode (bp_mode: number of
+// Sweeps t, t + 1, ... of the window while their mode (w32_mode: number of
 // nonzero threshold levels, screened or not) is 2 LEV + SCREEN; returns the
 // first sweep not run.  The mode is the schedule's, the same for every thread
 // of the block, so all of them leave at the same sweep and meet the same
@@ -382,15 +257,15 @@ __device__ __forceinline__ void bp_half_sweep(uint32_t* lds, const uint8_t* wl, 
 template <int NDIM, int LEV, bool SCREEN, bool FLIPS, bool STATS, bool EVEN2D>
 __device__ __forceinline__ int bp_sweeps(int t, const BpArgs& a, bool active, uint32_t* lds, const uint8_t* wl,
                                          const BpWalk& w, uint32_t quad0, uint32_t valid_lanes, uint32_t* fplanes,
-                                         uint32_t* extra, int nvalid, uint32_t& n_blocks, uint32_t& n_draws) {
+                                         uint32_t* extra, int nvalid, uint32_t& n_words, uint32_t& n_draws) {
   for (; t < a.t_end; ++t) {
     const uint32_t* tr = a.thr + (size_t)t * NDIM;
     const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
-    if (bp_mode<NDIM>(T1, T2, T3) != 2 * LEV + (SCREEN ? 1 : 0)) break;
+    if (w32_mode<NDIM>(T1, T2, T3) != 2 * LEV + (SCREEN ? 1 : 0)) break;
     for (uint32_t p = 0; p < 2u; ++p) {
       if (active)
         bp_half_sweep<NDIM, LEV, SCREEN, FLIPS, STATS, EVEN2D>(lds, wl, w, p, a.seed, (uint32_t)t, quad0, T1, T2, T3,
-                                                               valid_lanes, fplanes, n_blocks, n_draws);
+                                                               valid_lanes, fplanes, n_words, n_draws);
       __syncthreads();
     }
     if (FLIPS && ((t - a.t_begin) % a.flush_every == a.flush_every - 1 || t + 1 == a.t_end))
@@ -403,10 +278,10 @@ template <int NDIM, bool FLIPS, bool STATS, bool EVEN2D>
 __device__ __forceinline__ int bp_sweeps_mode(int mode, int t, const BpArgs& a, bool active, uint32_t* lds,
                                               const uint8_t* wl, const BpWalk& w, uint32_t quad0,
                                               uint32_t valid_lanes, uint32_t* fplanes, uint32_t* extra, int nvalid,
-                                              uint32_t& n_blocks, uint32_t& n_draws) {
+                                              uint32_t& n_words, uint32_t& n_draws) {
 #define ISING_BP_SWEEPS(LEV, SCREEN)                                                                              \
   bp_sweeps<NDIM, LEV, SCREEN, FLIPS, STATS, EVEN2D>(t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra, \
-                                                     nvalid, n_blocks, n_draws)
+                                                     nvalid, n_words, n_draws)
   switch (mode) {
     case 0:
       return ISING_BP_SWEEPS(0, false);
@@ -506,19 +381,19 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
   uint32_t fplanes[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) fplanes[k] = 0u;
-  uint32_t n_blocks = 0u, n_draws = 0u;
+  uint32_t n_words = 0u, n_draws = 0u;
   const uint32_t valid_lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
 
   int t = a.t_begin;
   while (t < a.t_end) {
     const uint32_t* tr = a.thr + (size_t)t * NDIM;
-    const int mode = bp_mode<NDIM>(tr[0], tr[1], NDIM == 3 ? tr[2] : 0u);
+    const int mode = w32_mode<NDIM>(tr[0], tr[1], NDIM == 3 ? tr[2] : 0u);
     if (even2d)
       t = bp_sweeps_mode<NDIM, FLIPS, STATS, true>(mode, t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra,
-                                                   nvalid, n_blocks, n_draws);
+                                                   nvalid, n_words, n_draws);
     else
       t = bp_sweeps_mode<NDIM, FLIPS, STATS, false>(mode, t, a, active, lds, wl, w, quad0, valid_lanes, fplanes,
-                                                    extra, nvalid, n_blocks, n_draws);
+                                                    extra, nvalid, n_words, n_draws);
   }
 
   // ---- unsatisfied bonds along +x, +y (+z): energy ---------------------------
@@ -559,7 +434,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_sweep_bp32(BpArgs a) {
   }
   // 64-bit totals (a block's can exceed 32 bits), one atomic per wave
   if (STATS) {
-    const uint64_t nb = wave_total((uint64_t)n_blocks), nd = wave_total((uint64_t)n_draws);
+    // eight Philox blocks per word that drew
+    const uint64_t nb = 8ull * wave_total((uint64_t)n_words), nd = wave_total((uint64_t)n_draws);
     if ((tid & 63) == 0 && (nb | nd)) {
       atomicAdd(&a.stats[0], (unsigned long long)nb);
       atomicAdd(&a.stats[1], (unsigned long long)nd);

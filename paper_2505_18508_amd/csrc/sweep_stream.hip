@@ -16,6 +16,7 @@
 #include "bitslice.hpp"
 #include "internal.hpp"
 #include "philox.hpp"
+#include "word32.hpp"
 
 namespace ising {
 namespace {
@@ -51,22 +52,6 @@ __device__ __forceinline__ uint32_t transpose_stage(uint32_t x, uint32_t lane, u
   return (hi & upper) | (lo & ~upper);                    // select without a branch
 }
 
-// The draws of a word's 32 replicas against the first LEV thresholds (LEV
-// >= 1; they decrease with k, so the nonzero ones are a prefix): bit j of
-// c_k = (Philox word of replica j) < T_k.
-template <int LEV>
-__device__ __forceinline__ void stream_draws(uint64_t seed, uint32_t ci, uint32_t t, uint32_t quad0, uint32_t T1,
-                                             uint32_t T2, uint32_t T3, uint32_t& c1, uint32_t& c2, uint32_t& c3) {
-#pragma unroll
-  for (int q = 7; q >= 0; --q) {
-    const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-    if (q == 7)
-      lt_shift_in4<LEV, true>(c1, c2, c3, r.v, T1, T2, T3);
-    else
-      lt_shift_in4<LEV>(c1, c2, c3, r.v, T1, T2, T3);
-  }
-}
-
 // A thread's strip: column m of K consecutive lines l0 .. l0+K-1 of one
 // plane (fewer for the last strip of a 2-D torus).  Going up the strip, the
 // other colour's word of the line just visited becomes the next line's -y
@@ -74,7 +59,7 @@ __device__ __forceinline__ void stream_draws(uint64_t seed, uint32_t ci, uint32_
 // neighbour, so a visit loads its own word, its weight signs, the x-shift
 // and +y neighbours (and, in 3-D, the +-z ones).  Flips are added into
 // bit-sliced counters fp[0..NP) (count = sum 2^b fp[b]).
-template <int NDIM, bool STATS, int K, int LEV, int NP>
+template <int NDIM, bool STATS, int K, int LEV, bool SCREEN, int NP>
 __device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, int p, uint32_t t, uint32_t strip,
                                              uint32_t m, uint32_t quad0, uint32_t lanes, uint32_t T1, uint32_t T2,
                                              uint32_t T3, uint32_t* fp, uint32_t& n_words, uint32_t& n_draws) {
@@ -136,29 +121,8 @@ __device__ __forceinline__ void stream_strip(const StreamArgs& a, uint32_t* w, i
       const uint32_t plus = ((wb >> d) & 1u) ? 0u : 0xFFFFFFFFu;  // all ones iff w = +1
       x[d] = xor3(s, nb[d], plus);                                // unsatisfied bonds
     }
-    uint32_t u0, u1, u2;
-    bond_count3<DEG>(x, u0, u1, u2);
-    uint32_t acc, k1, k2, k3 = 0u;
-    if (NDIM == 2) {
-      acc = u1 | u2;
-      k1 = u0 & ~acc;
-      k2 = ~(u0 | acc);
-    } else {
-      acc = u2 | (u1 & u0);
-      k1 = u1 & ~u0 & ~u2;
-      k2 = u0 & ~u1 & ~u2;
-      k3 = ~(u0 | u1 | u2);
-    }
-    uint32_t F = acc;
-    if (LEV > 0) {
-      uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-      stream_draws<(LEV > 0 ? LEV : 1)>(a.seed, ci, t, quad0, T1, T2, T3, c1, c2, c3);
-      F |= (k1 & c1) | (LEV >= 2 ? k2 & c2 : 0u) | (LEV >= 3 ? k3 & c3 : 0u);
-      if (STATS) {
-        n_words += 1u;
-        n_draws += __popc((k1 | (LEV >= 2 ? k2 : 0u) | (LEV >= 3 ? k3 : 0u)) & lanes);
-      }
-    }
+    const uint32_t F =
+        w32_decide<NDIM, LEV, SCREEN, STATS>(x, a.seed, ci, t, quad0, T1, T2, T3, lanes, n_words, n_draws);
     w[own] = s ^ F;
     Fk[k] = F;
     ym = x0;
@@ -217,7 +181,7 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
   const uint32_t lanes = nvalid == 32 ? 0xFFFFFFFFu : ((1u << nvalid) - 1u);
   const uint32_t* tr = a.thr + (size_t)t * NDIM;
   const uint32_t T1 = tr[0], T2 = tr[1], T3 = NDIM == 3 ? tr[2] : 0u;
-  const int lev = T1 == 0u ? 0 : T2 == 0u ? 1 : (NDIM == 2 || T3 == 0u) ? 2 : 3;
+  const int mode = w32_mode<NDIM>(T1, T2, T3);
   uint32_t fp[NP];
 #pragma unroll
   for (int b = 0; b < NP; ++b) fp[b] = 0u;
@@ -227,18 +191,33 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
     const uint32_t m = item - strip * hx;
     uint32_t* w = a.words + (size_t)g * L.n;
     const uint32_t quad0 = (uint32_t)(a.replica_offset + r0) >> 2;
-    if (lev == 0)
-      stream_strip<NDIM, STATS, K, 0, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
-                                          n_draws);
-    else if (lev == 1)
-      stream_strip<NDIM, STATS, K, 1, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
-                                          n_draws);
-    else if (NDIM == 2 || lev == 2)
-      stream_strip<NDIM, STATS, K, 2, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
-                                          n_draws);
-    else
-      stream_strip<NDIM, STATS, K, 3, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, n_words,
-                                          n_draws);
+#define ISING_STRIP(LEV, SCREEN)                                                                                 \
+  stream_strip<NDIM, STATS, K, LEV, SCREEN, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, \
+                                                n_words, n_draws)
+    switch (mode) {
+      case 0:
+        ISING_STRIP(0, false);
+        break;
+      case 2:
+        ISING_STRIP(1, false);
+        break;
+      case 3:
+        ISING_STRIP(1, true);
+        break;
+      case 4:
+        ISING_STRIP(2, false);
+        break;
+      case 5:
+        ISING_STRIP(2, true);
+        break;
+      case 6:
+        ISING_STRIP(NDIM == 3 ? 3 : 2, false);
+        break;
+      default:
+        ISING_STRIP(NDIM == 3 ? 3 : 2, true);
+        break;
+    }
+#undef ISING_STRIP
   }
   if (STATS) {  // block totals of Philox blocks (8 per word that drew) and draws, kept in the block's slot
     __shared__ uint32_t ws[kStreamBlock / 64][2];
