@@ -188,6 +188,55 @@ __device__ __forceinline__ uint32_t lt_select32_3(const uint32_t* u, uint32_t se
 }
 #undef ISING_SEL3_STEP
 #undef ISING_SEL_STEP
+// The chains above for the 16 words of a four-replica word (word 4 j + r:
+// site j, replica r), each replica with its own pair or triple of
+// thresholds: T_lo[r] / T_hi[r], or T1[r] / T2[r] / T3[r].  The selector bits
+// sit in bits 0..15 of sel (sel2, sel3) and results come out in bits 0..15.
+#define ISING_SEL16_STEP(TL, TH, U)              \
+  "v_cndmask_b32_e32 %1, %" #TL ", %" #TH ", vcc\n\t" \
+  "v_sub_co_u32_e32 %2, vcc, %" #U ", %1\n\t"   \
+  "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc\n\t"
+__device__ __forceinline__ uint32_t lt_select16(const uint32_t* u, uint32_t sel, const uint32_t* T_lo,
+                                                const uint32_t* T_hi) {
+  uint32_t c = sel << 16, t, d;
+  asm("v_add_co_u32_e32 %0, vcc, %0, %0\n\t"
+      ISING_SEL16_STEP(6, 10, 26) ISING_SEL16_STEP(5, 9, 25) ISING_SEL16_STEP(4, 8, 24) ISING_SEL16_STEP(3, 7, 23)
+      ISING_SEL16_STEP(6, 10, 22) ISING_SEL16_STEP(5, 9, 21) ISING_SEL16_STEP(4, 8, 20) ISING_SEL16_STEP(3, 7, 19)
+      ISING_SEL16_STEP(6, 10, 18) ISING_SEL16_STEP(5, 9, 17) ISING_SEL16_STEP(4, 8, 16) ISING_SEL16_STEP(3, 7, 15)
+      ISING_SEL16_STEP(6, 10, 14) ISING_SEL16_STEP(5, 9, 13) ISING_SEL16_STEP(4, 8, 12) ISING_SEL16_STEP(3, 7, 11)
+      : "+v"(c), "=&v"(t), "=&v"(d)
+      : "v"(T_lo[0]), "v"(T_lo[1]), "v"(T_lo[2]), "v"(T_lo[3]), "v"(T_hi[0]), "v"(T_hi[1]), "v"(T_hi[2]),
+        "v"(T_hi[3]), "v"(u[0]), "v"(u[1]), "v"(u[2]), "v"(u[3]), "v"(u[4]), "v"(u[5]), "v"(u[6]), "v"(u[7]),
+        "v"(u[8]), "v"(u[9]), "v"(u[10]), "v"(u[11]), "v"(u[12]), "v"(u[13]), "v"(u[14]), "v"(u[15])
+      : "vcc");
+  return c;
+}
+#undef ISING_SEL16_STEP
+#define ISING_SEL16_3_STEP(T1, T2, T3, U)         \
+  "v_cndmask_b32_e32 %2, %" #T1 ", %" #T3 ", vcc\n\t" \
+  "v_add_co_u32_e32 %1, vcc, %1, %1\n\t"          \
+  "v_cndmask_b32_e32 %2, %2, %" #T2 ", vcc\n\t"   \
+  "v_sub_co_u32_e32 %3, vcc, %" #U ", %2\n\t"    \
+  "v_addc_co_u32_e32 %0, vcc, %0, %0, vcc\n\t"
+__device__ __forceinline__ uint32_t lt_select16_3(const uint32_t* u, uint32_t sel2, uint32_t sel3, const uint32_t* T1,
+                                                  const uint32_t* T2, const uint32_t* T3) {
+  uint32_t c = sel3 << 16, s = sel2 << 16, t, d;
+  asm("v_add_co_u32_e32 %0, vcc, %0, %0\n\t"
+      ISING_SEL16_3_STEP(7, 11, 15, 31) ISING_SEL16_3_STEP(6, 10, 14, 30) ISING_SEL16_3_STEP(5, 9, 13, 29)
+      ISING_SEL16_3_STEP(4, 8, 12, 28) ISING_SEL16_3_STEP(7, 11, 15, 27) ISING_SEL16_3_STEP(6, 10, 14, 26)
+      ISING_SEL16_3_STEP(5, 9, 13, 25) ISING_SEL16_3_STEP(4, 8, 12, 24) ISING_SEL16_3_STEP(7, 11, 15, 23)
+      ISING_SEL16_3_STEP(6, 10, 14, 22) ISING_SEL16_3_STEP(5, 9, 13, 21) ISING_SEL16_3_STEP(4, 8, 12, 20)
+      ISING_SEL16_3_STEP(7, 11, 15, 19) ISING_SEL16_3_STEP(6, 10, 14, 18) ISING_SEL16_3_STEP(5, 9, 13, 17)
+      ISING_SEL16_3_STEP(4, 8, 12, 16)
+      : "+v"(c), "+v"(s), "=&v"(t), "=&v"(d)
+      : "v"(T1[0]), "v"(T1[1]), "v"(T1[2]), "v"(T1[3]), "v"(T2[0]), "v"(T2[1]), "v"(T2[2]), "v"(T2[3]),
+        "v"(T3[0]), "v"(T3[1]), "v"(T3[2]), "v"(T3[3]), "v"(u[0]), "v"(u[1]), "v"(u[2]), "v"(u[3]), "v"(u[4]),
+        "v"(u[5]), "v"(u[6]), "v"(u[7]), "v"(u[8]), "v"(u[9]), "v"(u[10]), "v"(u[11]), "v"(u[12]), "v"(u[13]),
+        "v"(u[14]), "v"(u[15])
+      : "vcc");
+  return c;
+}
+#undef ISING_SEL16_3_STEP
 #undef ISING_LT_SUB
 #undef ISING_LT_ADD
 #undef ISING_LT_SET

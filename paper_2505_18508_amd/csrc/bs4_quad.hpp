@@ -205,6 +205,23 @@ __device__ __forceinline__ void bs4_draws(uint64_t seed, uint32_t ci0, uint32_t 
   }
 }
 
+// The 16 Philox words of a word's four sites: u[4 j + r] = word r of site j
+// (sites 3 and 2, then 1 and 0, two blocks in lockstep).
+__device__ __forceinline__ void bs4_words(uint64_t seed, uint32_t ci0, uint32_t Lx, uint32_t q, uint32_t t,
+                                          uint32_t quad, uint32_t* u) {
+#pragma unroll
+  for (int j = 3; j >= 1; j -= 2) {
+    u32x4 ra, rb;
+    philox_lane_c0_x2(seed, ci0 + (uint32_t)j * Lx + (q ^ 1u), ci0 + (uint32_t)(j - 1) * Lx + q, t, quad,
+                      kTagMetropolis, ra, rb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      u[4 * j + r] = ra.v[r];
+      u[4 * (j - 1) + r] = rb.v[r];
+    }
+  }
+}
+
 // Flip mask of a word from its bond counts: dE = 2 deg - 4u, flip when
 // u >= deg/2, else k = deg/2 - u and the replica flips iff its draw is below
 // T_k.  rows masks the lanes of real sites, q is o of the word's first site.
@@ -223,6 +240,21 @@ __device__ __forceinline__ uint32_t bs4_decide(uint32_t u0, uint32_t u1, uint32_
     k1 = u1 & ~u0 & ~u2;
     k2 = u0 & ~u1 & ~u2;
     k3 = ~(u0 | u1 | u2);
+  }
+  if (LEV >= 2) {  // the levels share one chain; each replica's level bits pick its threshold
+    const uint32_t need = k1 | k2 | (LEV >= 3 ? k3 : 0u);
+    if (STATS) {
+      n_blocks += 4u;
+      n_draws += __popc(need & valid16 & rows);
+    }
+    uint32_t u[16];
+    bs4_words(a.seed, ci0, Lx, q, (uint32_t)t, quad, u);
+    const uint32_t s1[4] = {T1, T1, T1, T1}, s2[4] = {T2, T2, T2, T2}, s3[4] = {T3, T3, T3, T3};
+    const uint32_t* t1 = PT ? th.T[0] : s1;
+    const uint32_t* t2 = PT ? th.T[1] : s2;
+    const uint32_t* t3 = PT ? th.T[2] : s3;
+    const uint32_t c = LEV == 2 ? lt_select16(u, k2, t1, t2) : lt_select16_3(u, k2, k3, t1, t2, t3);
+    return (acc | (need & c)) & rows;
   }
   uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
   if (LEV > 0) {
