@@ -257,6 +257,26 @@ def test_threshold_levels_vanishing_and_zero_temperature(dev, layout, dims):
     assert oracle.threshold(12.0, 1) == 0 and oracle.threshold(1.9, 3) == 0 and oracle.threshold(1.8, 3) > 0
 
 
+# beta on either side of where the smallest nonzero threshold crosses 2^21, the bound below
+# which the 32-replica kernels screen their compares per wave: T_2 at 0.953 / 0.9531 (2-D),
+# T_3 at 0.6353 / 0.6356 (3-D); hot and cold sweeps between them
+SCREEN_TABLE = [0.953, 0.9531, 0.953, 0.9532, 0.6353, 0.6356, 0.6353, 0.3, 2.0, 0.6356, 0.9531, 0.953]
+
+
+@pytest.mark.parametrize("dims", [[20, 30], [6, 8, 10]])
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_sweeps_alternating_across_the_compare_screen_bound(dev, layout, dims):
+    n = oracle.n_sites(dims)
+    table = np.array(SCREEN_TABLE * 5)
+    s0 = inputs.random_spins(14, 45, n)
+    w = inputs.random_weights(15, len(dims) * n)
+    gpu = run_gpu(dims, 0, 93, 45, len(table), schedule="table", table=table, spins0=s0, weights=w, layout=layout)
+    orc = run_oracle(dims, 0, 93, 45, len(table), schedule="table", table=table, spins0=s0, weights=w)
+    assert_same(gpu, orc)
+    assert oracle.threshold(0.953, 2) >= 2**21 > oracle.threshold(0.9531, 2)
+    assert oracle.threshold(0.6353, 3) >= 2**21 > oracle.threshold(0.6356, 3)
+
+
 @pytest.mark.parametrize("dims", [[20, 30], [6, 8, 10], [6, 10]])
 @pytest.mark.parametrize("layout", ["bs4", "i8"])
 def test_replica_thresholds_mixing_zero_and_hot_replicas(dev, layout, dims):
