@@ -11,7 +11,8 @@
 // bit-sliced counter u (0..deg), and derives dE = 2 deg - 4u: replicas with
 // u >= deg/2 (dE <= 0) flip, a replica with dE = 4k > 0 flips iff its Philox
 // word of (site, sweep, replica >> 2, tag 0) is below T_k(sweep).  The eight
-// Philox blocks of a word serve its eight replica quads.  Fields are
+// Philox blocks of a word serve its eight replica quads; the decision and its
+// compare chains are shared with the streamed kernel (word32.hpp).  Fields are
 // recomputed from the neighbours' words at every visit, so nothing but spins
 // lives on chip.  Same-colour sites are never neighbours on an even torus, so
 // the parallel update equals the sequential sweep bit for bit.
@@ -282,23 +283,21 @@ __device__ __forceinline__ int bp_sweeps_mode(int mode, int t, const BpArgs& a, 
 #define ISING_BP_SWEEPS(LEV, SCREEN)                                                                              \
   bp_sweeps<NDIM, LEV, SCREEN, FLIPS, STATS, EVEN2D>(t, a, active, lds, wl, w, quad0, valid_lanes, fplanes, extra, \
                                                      nvalid, n_words, n_draws)
+  // the modes w32_mode returns: 0, 3, 5 and 4 (2-D) or 6, 7 (3-D)
   switch (mode) {
     case 0:
       return ISING_BP_SWEEPS(0, false);
-    case 2:
-      return ISING_BP_SWEEPS(1, false);
     case 3:
       return ISING_BP_SWEEPS(1, true);
-    case 4:
-      return ISING_BP_SWEEPS(2, false);
     case 5:
       return ISING_BP_SWEEPS(2, true);
   }
-  if (NDIM == 3) {
-    if (mode == 6) return ISING_BP_SWEEPS(NDIM == 3 ? 3 : 2, false);
-    return ISING_BP_SWEEPS(NDIM == 3 ? 3 : 2, true);
+  if constexpr (NDIM == 2) {
+    return ISING_BP_SWEEPS(2, false);
+  } else {
+    if (mode == 6) return ISING_BP_SWEEPS(3, false);
+    return ISING_BP_SWEEPS(3, true);
   }
-  return ISING_BP_SWEEPS(2, false);  // not reached: a 2-D mode is at most 5
 #undef ISING_BP_SWEEPS
 }
 

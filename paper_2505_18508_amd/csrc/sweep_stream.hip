@@ -194,28 +194,19 @@ __global__ void __launch_bounds__(kStreamBlock) k_halfsweep_stream(StreamArgs a,
 #define ISING_STRIP(LEV, SCREEN)                                                                                 \
   stream_strip<NDIM, STATS, K, LEV, SCREEN, NP>(a, w, p, (uint32_t)t, strip, m, quad0, lanes, T1, T2, T3, fp, \
                                                 n_words, n_draws)
-    switch (mode) {
-      case 0:
-        ISING_STRIP(0, false);
-        break;
-      case 2:
-        ISING_STRIP(1, false);
-        break;
-      case 3:
-        ISING_STRIP(1, true);
-        break;
-      case 4:
-        ISING_STRIP(2, false);
-        break;
-      case 5:
-        ISING_STRIP(2, true);
-        break;
-      case 6:
-        ISING_STRIP(NDIM == 3 ? 3 : 2, false);
-        break;
-      default:
-        ISING_STRIP(NDIM == 3 ? 3 : 2, true);
-        break;
+    // the modes w32_mode returns: 0, 3, 5 and 4 (2-D) or 6, 7 (3-D)
+    if (mode == 0) {
+      ISING_STRIP(0, false);
+    } else if (mode == 3) {
+      ISING_STRIP(1, true);
+    } else if (mode == 5) {
+      ISING_STRIP(2, true);
+    } else if constexpr (NDIM == 2) {
+      ISING_STRIP(2, false);
+    } else if (mode == 6) {
+      ISING_STRIP(3, false);
+    } else {
+      ISING_STRIP(3, true);
     }
 #undef ISING_STRIP
   }

@@ -20,11 +20,15 @@ constexpr uint32_t kW32ScreenBelow = 1u << 21;
 
 // A sweep's mode: 2 x (number of nonzero thresholds) + 1 when its compares
 // are screened.  A function of the schedule alone, the same in every thread.
+// Fewer nonzero levels than deg/2 are always screened: the thresholds of one
+// beta are powers of exp(-4 beta), so a vanished level leaves the others
+// below 2^16 (one level) or 2^11 (two of three), far under the bound.  The
+// modes are thus 0, 3 and, in 2-D, 4, 5 or, in 3-D, 5, 6, 7.
 template <int NDIM>
 __device__ __forceinline__ int w32_mode(uint32_t T1, uint32_t T2, uint32_t T3) {
   const int lev = sweep_levels<NDIM>(T1, T2, T3);
   const uint32_t low = lev == 1 ? T1 : lev == 2 ? T2 : T3;
-  return 2 * lev + (lev > 0 && low < kW32ScreenBelow ? 1 : 0);
+  return 2 * lev + (lev > 0 && (lev < NDIM || low < kW32ScreenBelow) ? 1 : 0);
 }
 
 // The 32 Philox words of a site word: u[j] for replica j.
@@ -59,8 +63,9 @@ __device__ __forceinline__ uint32_t w32_screened_lt(const uint32_t* u, uint32_t 
 // flips outright and u < deg/2 is level k = deg/2 - u.  LEV = number of
 // nonzero thresholds of the sweep (a prefix, as they decrease with k); a
 // level past LEV never flips.  SCREEN runs each level's own chain only in
-// waves where some word falls below its threshold; otherwise two or three
-// levels share one chain whose threshold each replica's level bits pick.
+// waves where some word falls below its threshold; otherwise (all deg/2
+// levels nonzero, w32_mode) two or three levels share one chain whose
+// threshold each replica's level bits pick.
 // STATS: words that drew (n_words) and draws that decide (n_draws) over the
 // valid replica lanes.
 template <int NDIM, int LEV, bool SCREEN, bool STATS>
@@ -87,23 +92,12 @@ __device__ __forceinline__ uint32_t w32_decide(const uint32_t* x, uint64_t seed,
     n_words += 1u;
     n_draws += __popc(need & valid_lanes);
   }
-  if (!SCREEN && LEV >= 2) {
+  static_assert(SCREEN || LEV == 0 || LEV == NDIM, "unscreened sweeps with draws have every level nonzero");
+  if (!SCREEN) {
     uint32_t u[32];
     w32_draws(seed, ci, t, quad0, u);
     const uint32_t c = LEV == 2 ? lt_select32(u, k2, T1, T2) : lt_select32_3(u, k2, k3, T1, T2, T3);
     return acc | (need & c);
-  }
-  if (!SCREEN) {  // one level: its chain, fed block by block
-    uint32_t c1 = 0u, c2 = 0u, c3 = 0u;
-#pragma unroll
-    for (int q = 7; q >= 0; --q) {
-      const u32x4 r = philox_lane_c0(seed, ci, t, quad0 + (uint32_t)q, kTagMetropolis);
-      if (q == 7)
-        lt_shift_in4<1, true>(c1, c2, c3, r.v, T1, T2, T3);
-      else
-        lt_shift_in4<1>(c1, c2, c3, r.v, T1, T2, T3);
-    }
-    return acc | (k1 & c1);
   }
   uint32_t u[32];
   w32_draws(seed, ci, t, quad0, u);
