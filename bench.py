@@ -92,23 +92,97 @@ OPS_PER_DRAW = 40 / 4
 OPS_PER_ATTEMPT = 3
 
 
+# the reference copy of --calibrate-copy: a kernel of known HBM traffic
+# (this many bytes read and written) that scales the counters of the same run
+CALIBRATION_COPY_BYTES = 256 << 20
+
+
+def traffic_path():
+    return os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_closure(src):
+    """A kernel source file (repository-relative) and, transitively, every
+    header it includes with #include "..." (beside the including file, else
+    under include/), in discovery order."""
+    import re
+
+    order, seen, todo = [], set(), [src]
+    while todo:
+        f = todo.pop(0)
+        if f in seen:
+            continue
+        seen.add(f)
+        order.append(f)
+        for inc in re.findall(r'^#include "([^"]+)"', open(os.path.join(ROOT, f)).read(), re.M):
+            path = os.path.normpath(os.path.join(os.path.dirname(f), inc))
+            if not os.path.exists(os.path.join(ROOT, path)):
+                path = os.path.normpath(os.path.join("include", inc))
+            if os.path.exists(os.path.join(ROOT, path)):
+                todo.append(path)
+    return order
+
+
+def sources_digest(files):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed counter profile, or None when
     there is none or the kernel source changed since it was taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = traffic_path()
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get("%s/%s" % (kernel, workload))
     if rec is None:
         return None
-    h = hashlib.sha256()
-    for f in rec["sources"]:  # the kernel's source file and every header it includes
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    # the kernel's source file and every header it includes
+    if sources_digest(rec["sources"]) != rec["sources_sha256"]:
         return None
     return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def counter_per_dispatch(run_dir, counter, kernel):
+    """Per-dispatch values (summed over the device's instances) of one counter
+    for the dispatches whose kernel name contains `kernel`, in dispatch order,
+    from a rocprofv3 --pmc run written with -o run --output-format csv."""
+    import csv
+
+    per, names = {}, {}
+    for r in csv.DictReader(open(os.path.join(run_dir, "run_counter_collection.csv"))):
+        if r["Counter_Name"] == counter:
+            d = int(r["Dispatch_Id"])
+            per[d] = per.get(d, 0.0) + float(r["Counter_Value"])
+            names[d] = r["Kernel_Name"]
+    return [per[d] for d in sorted(per) if kernel in names[d]]
+
+
+def record_traffic(key, source, kernel, fetch_run, write_run, profile, per_sequence=None):
+    """Store a kernel's HBM bytes per launch in profiles/traffic.json from a
+    FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled by what
+    the counter reads for the run's calibration copy (its largest copy
+    dispatch), with the digest of the kernel's source closure.  One launch is
+    the last matching dispatch, or with per_sequence = N the mean dispatch
+    times N (a launch sequence of N half-sweeps)."""
+    kib = CALIBRATION_COPY_BYTES / 1024.0
+    sides = {}
+    for side, run, counter in (("fetch", fetch_run, "FETCH_SIZE"), ("write", write_run, "WRITE_SIZE")):
+        vals = counter_per_dispatch(run, counter, kernel)
+        copy = max(counter_per_dispatch(run, counter, "copyBuffer"))
+        raw = sum(vals) / len(vals) * per_sequence if per_sequence else vals[-1]
+        sides[side] = raw * 1024 * (kib / copy)
+    path = traffic_path()
+    recs = json.load(open(path)) if os.path.exists(path) else {}
+    files = source_closure(source)
+    recs[key] = dict(fetch_bytes=sides["fetch"], write_bytes=sides["write"], sources=files,
+                     sources_sha256=sources_digest(files), profile=profile)
+    json.dump(recs, open(path, "w"), indent=1)
+    return recs[key]
 
 
 def batch_layout(ising, g, run):
@@ -334,7 +408,21 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default=DEFAULT_WORKLOAD)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device (a reference kernel of known traffic for counters)")
+    ap.add_argument("--record-traffic", metavar="KERNEL/WORKLOAD", default=None,
+                    help="no GPU: store profiles/traffic.json's record from the rocprofv3 runs named below")
+    ap.add_argument("--source", help="with --record-traffic: the kernel's source file")
+    ap.add_argument("--kernel", help="with --record-traffic: a substring of the dispatches' kernel name")
+    ap.add_argument("--fetch-run", help="with --record-traffic: the FETCH_SIZE run's output folder")
+    ap.add_argument("--write-run", help="with --record-traffic: the WRITE_SIZE run's output folder")
+    ap.add_argument("--profile", help="with --record-traffic: the summary the record belongs to")
+    ap.add_argument("--per-sequence", type=int, default=None,
+                    help="with --record-traffic: launches per sequence (mean dispatch x N); else the last dispatch")
     args = ap.parse_args()
+    if args.record_traffic:
+        rec = record_traffic(args.record_traffic, args.source, args.kernel, args.fetch_run, args.write_run,
+                             args.profile, args.per_sequence)
+        print(json.dumps({args.record_traffic: rec}))
+        return
     global WORKLOAD
     WORKLOAD = WORKLOADS[args.workload]
     if args.gpus != 1:
@@ -360,7 +448,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
-        src = torch.ones(256 << 20, dtype=torch.uint8, device=dev)
+        src = torch.ones(CALIBRATION_COPY_BYTES, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()

@@ -40,6 +40,46 @@ def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic(kernel, workload) is None
 
 
+def test_record_traffic_scales_each_counter_by_the_calibration_copy(tmp_path, monkeypatch):
+    """A record holds the kernel's FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    scaled by the ratio of the calibration copy's size to what the counter read
+    for that copy: the last matching dispatch for one launch, or the mean times
+    the launches of a sequence; with the closure and digest of its sources."""
+    import shutil as sh
+
+    src = "paper_2505_18508_amd/csrc/sweep_batch.hip"
+    for f in bench.source_closure(src):
+        os.makedirs(tmp_path / os.path.dirname(f), exist_ok=True)
+        sh.copy(os.path.join(ROOT, f), tmp_path / f)
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    kib = bench.CALIBRATION_COPY_BYTES / 1024
+
+    def run(name, counter, copy_kib, values):
+        d = tmp_path / name
+        os.makedirs(d)
+        rows = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+        rows.append("1,__amd_rocclr_copyBuffer,%s,%r" % (counter, copy_kib))
+        for i, v in enumerate(values):  # two instances of the counter per dispatch
+            rows.append('%d,"void k_x<2>(Args)",%s,%r' % (i + 2, counter, v / 2))
+            rows.append('%d,"void k_x<2>(Args)",%s,%r' % (i + 2, counter, v / 2))
+        rows.append('9,"void k_other(int)",%s,1000.0' % counter)
+        (d / "run_counter_collection.csv").write_text("\n".join(rows) + "\n")
+        return str(d)
+
+    fetch = run("f", "FETCH_SIZE", kib / 2, [100.0, 300.0])  # the copy reads half its bytes: x2
+    write = run("w", "WRITE_SIZE", kib, [50.0, 70.0])
+    rec = bench.record_traffic("k_x/w1", src, "k_x<2>", fetch, write, "profiles/x.md")
+    assert rec["fetch_bytes"] == pytest.approx(300.0 * 1024 * 2)
+    assert rec["write_bytes"] == pytest.approx(70.0 * 1024)
+    assert rec["sources"] == bench.source_closure(src) and "include/ising.h" in rec["sources"]
+    assert bench.measured_traffic("k_x", "w1") == pytest.approx((600.0 + 70.0) * 1024)
+    rec = bench.record_traffic("k_x/w2", src, "k_x<2>", fetch, write, "profiles/x.md", per_sequence=10)
+    assert rec["fetch_bytes"] == pytest.approx(200.0 * 10 * 1024 * 2)
+    assert rec["write_bytes"] == pytest.approx(60.0 * 10 * 1024)
+    assert set(json.load(open(bench.traffic_path()))) == {"k_x/w1", "k_x/w2"}
+
+
 def test_traffic_record_lists_every_included_source():
     """The record's sources are the kernel file and the transitive closure of
     its quoted includes, so no header the kernel is built from can change
