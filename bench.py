@@ -419,6 +419,9 @@ def main():
                     help="with --record-traffic: launches per sequence (mean dispatch x N); else the last dispatch")
     args = ap.parse_args()
     if args.record_traffic:
+        missing = [o for o in ("source", "kernel", "fetch_run", "write_run", "profile") if not getattr(args, o)]
+        if missing:
+            ap.error("--record-traffic needs " + ", ".join("--" + o.replace("_", "-") for o in missing))
         rec = record_traffic(args.record_traffic, args.source, args.kernel, args.fetch_run, args.write_run,
                              args.profile, args.per_sequence)
         print(json.dumps({args.record_traffic: rec}))
