@@ -122,7 +122,9 @@ def test_3d_uneven_batch_matches_single_runs_and_oracle(ising):
 
 def test_full_size_uneven_batch_matches_single_runs(ising):
     """The four tori of 5,000-20,000 spins with 256-4,096 replicas and
-    5,000-20,000 sweeps in one persistent launch."""
+    5,000-20,000 sweeps in one persistent launch: every replica equal to
+    single-instance runs of another packing, and the first and last replica of
+    each instance equal to the oracle over its whole schedule."""
     import torch
 
     specs = [([50, 100], 11, 111, 256, 5000, 0, 5000, "geometric", 0.05, 4.0),
@@ -136,6 +138,27 @@ def test_full_size_uneven_batch_matches_single_runs(ising):
     for g, run in zip(graphs, runs):
         assert_run_equal(run, single(ising, g, run))
     b.close()
+    # the oracle recomputes the first and the last replica of every instance end to end,
+    # one replica per host thread
+    import concurrent.futures
+    import os
+
+    def orc(task):
+        k, r = task
+        dims, wseed, seed, R, S = specs[k][:5]
+        w = oracle.random_weights(wseed, len(dims) * oracle.n_sites(dims))
+        s, fl = oracle.run(dims, w, seed, 1, S, 0, S, oracle.SCHED_GEOMETRIC, 0.05, 4.0, replica_begin=r)
+        cut, en = oracle.cut_energy(dims, w, s)
+        return task, (s, cut, en, fl)
+
+    tasks = [(k, r) for k, spec in enumerate(specs) for r in (0, spec[3] - 1)]
+    print("oracle replicas (instance, replica):", tasks, flush=True)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        for (k, r), (s, cut, en, fl) in ex.map(orc, tasks):
+            run = runs[k]
+            assert (run["spins"][r:r + 1].cpu().numpy() == s).all(), (k, r)
+            assert run["cut"][r].item() == cut[0] and run["energy"][r].item() == en[0], (k, r)
+            assert (run["flips"][r:r + 1].cpu().numpy().astype(np.uint32) == fl).all(), (k, r)
 
 
 def test_graph_replays_match_eager(ising):
