@@ -33,7 +33,7 @@ EXPORTED = [
     "ising_adam_step", "ising_feature_stats", "ising_cull_clone", "ising_energy_score", "ising_schedule_beta",
     "ising_batch_create", "ising_batch_run", "ising_batch_info", "ising_batch_destroy", "ising_final_cut_score",
     "ising_pt_create", "ising_pt_run", "ising_pt_state", "ising_pt_destroy", "ising_standardize_groups",
-    "ising_cut_labels",
+    "ising_cut_labels", "ising_compare_chains",
 ]
 N_FEATURES, MLP_HIDDEN, MLP_PARAMS = 16, 64, 5313
 TRACK_WORDS = 4  # ising_track = 32 bytes: held as int64 [R][4]
@@ -95,6 +95,8 @@ def lib():
         L.ising_eval_cut.argtypes = [vp, vp, i64, vp, vp, vp]
         L.ising_thresholds.argtypes = [ctypes.POINTER(RunParams), i32, vp]
         L.ising_philox_dump.argtypes = [u64, vp, i64, vp, vp]
+        u32 = ctypes.c_uint32
+        L.ising_compare_chains.argtypes = [i64, vp, vp, vp, u32, u32, u32, vp, vp]
         L.ising_last_error.argtypes = []
         L.ising_last_error.restype = ctypes.c_char_p
         f32 = ctypes.c_float
@@ -344,6 +346,18 @@ def philox_dump(key, ctr, out, stream=None):
         raise ValueError("ctr must be [m][4]")
     _check(lib().ising_philox_dump(int(key), _dev(ctr, "ctr", I32), m, _dev(out, "out", I32, 4 * m),
                                    _stream(stream)))
+
+
+def compare_chains(u, sel2, sel3, T1, T2, T3, out, stream=None):
+    """ising_compare_chains: the kernels' threshold compare chains on u
+    uint32/int32 device [n][32] with level bits sel2, sel3 [n]; out [n][8]."""
+    n = u.shape[0]
+    if u.dim() != 2 or u.shape[1] != 32:
+        raise ValueError("u must be [n][32]")
+    _check(lib().ising_compare_chains(n, *_devs((u, "u", I32, 32 * n), (sel2, "sel2", I32, n),
+                                               (sel3, "sel3", I32, n)),
+                                      int(T1) & 0xFFFFFFFF, int(T2) & 0xFFFFFFFF, int(T3) & 0xFFFFFFFF,
+                                      _dev(out, "out", I32, 8 * n), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ising.h"
+#include "ising_checks.h"
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -296,6 +297,9 @@ int check_device(const ising_graph* g) {
   return ISING_OK;
 }
 
+// chains.hip (declared here, not in internal.hpp: only this file calls it)
+hipError_t launch_compare_chains(int64_t n, const uint32_t* u, const uint32_t* sel2, const uint32_t* sel3,
+                                 uint32_t T1, uint32_t T2, uint32_t T3, uint32_t* out, hipStream_t stream);
 }  // namespace ising
 
 extern "C" {
@@ -775,6 +779,15 @@ int ising_philox_dump(uint64_t key, const uint32_t* ctr, int64_t m, uint32_t* ou
   if (m > 0 && (!ctr || !out)) return fail(ISING_E_ARG, "ctr or out is NULL");
   hipError_t e = ising::launch_philox_dump(key, ctr, m, out, (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(e, "philox kernel launch");
+  return ISING_OK;
+}
+
+int ising_compare_chains(int64_t n, const uint32_t* u, const uint32_t* sel2, const uint32_t* sel3, uint32_t T1,
+                         uint32_t T2, uint32_t T3, uint32_t* out, void* stream) {
+  if (n < 0 || n > ((int64_t)1 << 31)) return fail(ISING_E_ARG, "n out of range");
+  if (n > 0 && (!u || !sel2 || !sel3 || !out)) return fail(ISING_E_ARG, "u, sel2, sel3 or out is NULL");
+  hipError_t e = ising::launch_compare_chains(n, u, sel2, sel3, T1, T2, T3, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(e, "compare-chain kernel launch");
   return ISING_OK;
 }
 
