@@ -55,8 +55,10 @@ int sweep_bs4_default_block(const Lattice& L, int n_replicas, int cus, size_t ld
   const int quads = (n_replicas + 3) / 4;
   if (full <= 0 || quads < 4 * cus || 2 * sweep_bs4_lds_bytes(L) > lds_per_cu) return full;
   // four or more quads per compute unit: blocks of at most 512 threads (8
-  // waves, so that four blocks fit the CU's 32 wave slots), whose co-resident
-  // blocks overlap each other's barriers better than the largest block does
+  // waves: the kernel's registers leave a CU 16 wave slots, four waves per
+  // SIMD, so two such blocks fit where a 9-wave block leaves room for one),
+  // whose co-resident blocks overlap each other's barriers better than the
+  // largest block does
   const int lp = 512 / L.hx;
   return sweep_bs4_block(L, (lp < 1 ? 1 : lp) * L.hx);
 }
